@@ -1,0 +1,185 @@
+"""Throughput of the incompressible Navier-Stokes step on one MI355X.
+
+Workload: the 512^3 lid-driven cavity (Re 1000, dt 3e-4, gamma 0.5,
+omega 1.7, tol 1e-8, 200 red-black SOR sweeps per step), state resident in
+HBM, synthetic start (fluid at rest, lid (1,0,0) on z = 1).  Each timed
+step is the whole step (boundary fill, predictor, rhs, Poisson solve,
+projection).  ``value`` is the FP32-mixed form (FP32 fields and sweeps,
+FP64 pressure, norms and defect correction); the FP64 form is measured on
+the same grid and reported beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 512] [--no-cpu]
+
+Prints one JSON line.  ``roofline`` covers the dominant kernel (the fused
+red-black sweep): algorithmic bytes per launch over its average duration,
+measured with HIP events on the handle's stream inside the timed region.
+``cpu_baseline`` times the FP64 oracle on a bounded sample of the same
+workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "Mcell-steps/s and HBM GB/s, 512^3 NS step, FP32-mixed vs FP64 on 1 GPU"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def measure(prm, steps, warmup):
+    import torch
+
+    from paper_1201_2118_amd import abi
+    from paper_1201_2118_amd.solver import Solver
+
+    prm = dict(prm, flags=abi.NS_TIMING)
+    s = Solver(prm, device="cuda:0")
+    if warmup:
+        s.step(warmup)
+    t0 = s.timing()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    t1 = s.timing()
+    st = s.stats()
+    s.close()
+    n = prm["nx"] * prm["ny"] * prm["nz"]
+    secs = b - a
+    sor_ms = t1.ms[abi.NS_T_SOR] - t0.ms[abi.NS_T_SOR]
+    sor_launches = t1.launches[abi.NS_T_SOR] - t0.launches[abi.NS_T_SOR]
+    sor_bytes = t1.sor_bytes - t0.sor_bytes
+    stage_ms = {name: (t1.ms[i] - t0.ms[i]) / steps for name, i in
+                (("bc", abi.NS_T_BC), ("fgh", abi.NS_T_FGH), ("rhs", abi.NS_T_RHS),
+                 ("sor", abi.NS_T_SOR), ("defect", abi.NS_T_DEFECT), ("project", abi.NS_T_PROJECT),
+                 ("other", abi.NS_T_OTHER))}
+    return {
+        "mcells": n * steps / secs / 1e6,
+        "ms_per_step": secs * 1e3 / steps,
+        "sor_avg_ms": sor_ms / max(sor_launches, 1),
+        "sor_launches_per_step": sor_launches / steps,
+        "sor_gbs": sor_bytes / (sor_ms * 1e-3) / 1e9 if sor_ms > 0 else 0.0,
+        "sor_bytes_per_launch": sor_bytes / max(sor_launches, 1),
+        "stage_ms": stage_ms,
+        "stats": st,
+    }
+
+
+def step_bytes(n, sweeps, mixed, outers=1):
+    """Algorithmic HBM bytes of one step per cell (minimum single pass per
+    stage): FP64 112 + 24 S; mixed 60 + 12 S + 28 O."""
+    if mixed:
+        return n * (60 + 12 * sweeps + 28 * outers)
+    return n * (112 + 24 * sweeps)
+
+
+def cpu_baseline(prm):
+    """The FP64 oracle, untuned, on this host: one step of the same grid
+    with 2 SOR sweeps, plus 2 further sweep+residual passes to price a sweep;
+    scaled to the workload's sweeps per step."""
+    import numpy as np
+
+    import oracle
+
+    p = dict(prm, tol=0.0, itermax=2)
+    o = oracle.Oracle(p)
+    a = time.perf_counter()
+    o.run(1)
+    t_step2 = time.perf_counter() - a
+    a = time.perf_counter()
+    for _ in range(2):
+        o.sor_sweep(o.p, o.rhs)
+        o.residual(o.p, o.rhs)
+    t_sweep = (time.perf_counter() - a) / 2
+    sweeps = prm["itermax"]
+    t_full = t_step2 + (sweeps - 2) * t_sweep
+    n = prm["nx"] * prm["ny"] * prm["nz"]
+    del o
+    return {"value": n / t_full / 1e6, "unit": "Mcell-steps/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"one {prm['nx']}^3 step with 2 sweeps ({t_step2:.1f} s) plus 2 sweep+residual "
+                      f"passes ({t_sweep:.2f} s each), scaled to {sweeps} sweeps per step; FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the domain would be "
+              "split into z slabs with halo exchange; see the design notes). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import nsworkloads as W
+
+    prm, _ = W.cavity_512()
+    if args.n != 512:
+        prm = W.cavity(args.n, re=1000.0, dt=3e-4, tol=1e-8)
+    n = prm["nx"] * prm["ny"] * prm["nz"]
+    res = {}
+    for form in (["mixed", "fp64"] if args.only == "both" else [args.only]):
+        log(f"{form}: {args.n}^3, warmup {args.warmup}, steps {args.steps}")
+        r = measure(dict(prm, precision=form), args.steps, args.warmup)
+        st = r["stats"]
+        sweeps = st["sweeps_total"] / max(st["steps"], 1)
+        r["alg_gbs"] = step_bytes(n, sweeps, form == "mixed", max(st["outer_max"], 1)) / (r["ms_per_step"] * 1e-3) / 1e9
+        log(f"{form}: {r['mcells']:.1f} Mcell-steps/s, {r['ms_per_step']:.1f} ms/step, "
+            f"sor {r['sor_avg_ms']:.3f} ms/launch = {r['sor_gbs']:.0f} GB/s")
+        res[form] = r
+    head = res.get("mixed") or res["fp64"]
+    dom = head
+    roof = {"bound": "hbm", "achieved": round(dom["sor_gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(dom["sor_gbs"] / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "red-black SOR sweep (%s)" % ("FP32" if head is res.get("mixed") else "FP64"),
+            "bytes_per_launch": dom["sor_bytes_per_launch"], "avg_launch_ms": round(dom["sor_avg_ms"], 5)}
+    out = {
+        "metric": METRIC,
+        "value": round(head["mcells"], 2),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head is res.get("mixed") else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"lid-driven cavity {args.n}^3", "re": prm["re"], "dt": prm["dt"],
+                   "gamma": prm["gamma"], "omega": prm["omega"], "tol": prm["tol"],
+                   "itermax": prm["itermax"], "precision": "mixed" if head is res.get("mixed") else "fp64"},
+        "hbm_gbs_algorithmic": round(head["alg_gbs"], 1),
+        "sweeps_per_step": head["stats"]["sweeps_total"] / max(head["stats"]["steps"], 1),
+        "stage_ms": {k: round(v, 4) for k, v in head["stage_ms"].items()},
+        "roofline": roof,
+    }
+    if "fp64" in res and head is not res["fp64"]:
+        f = res["fp64"]
+        out["fp64"] = {"value": round(f["mcells"], 2), "ms_per_step": round(f["ms_per_step"], 3),
+                       "hbm_gbs_algorithmic": round(f["alg_gbs"], 1), "sor_gbs": round(f["sor_gbs"], 1),
+                       "sor_avg_ms": round(f["sor_avg_ms"], 5),
+                       "stage_ms": {k: round(v, 4) for k, v in f["stage_ms"].items()}}
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(prm)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,493 @@
+// kernels.hip -- gfx950 stencil kernels of the staggered-grid Navier-Stokes
+// step other than the Poisson sweeps: boundary / ghost fill, momentum
+// predictor, Poisson right-hand side, projection, adaptive dt.
+//
+// Every kernel streams the padded [nz+2][ny+2][nx+2] fields with
+// consecutive lanes on consecutive x, so each wave64 reads 64 contiguous
+// values per row (512 B in FP64).  Stencil neighbours are re-read through
+// the L1/L2 caches.  FP32-stored fields (mixed precision) are widened to
+// FP64 for the arithmetic.
+#include <hip/hip_runtime.h>
+
+#include "ns_internal.h"
+#include "reduce.h"
+
+namespace ns {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(long n, int cap = 8192) {
+  long b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  return (int)(b < cap ? b : cap);
+}
+
+// Flattened interior-cell loop: t -> (i, j, k) in [1, nx] x [1, ny] x [1, nz].
+struct Cell {
+  int i, j, k;
+  long c;
+};
+__device__ __forceinline__ Cell cell_of(const Geo& g, long t) {
+  Cell r;
+  long row = t / g.nx;
+  r.i = (int)(t - row * g.nx) + 1;
+  r.k = (int)(row / g.ny) + 1;
+  r.j = (int)(row - (long)(r.k - 1) * g.ny) + 1;
+  r.c = (long)r.k * g.sxy + (long)r.j * g.sx + r.i;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Ghost / boundary fill.  Walls: wall-normal faces := 0 (full extent), then
+// tangential ghosts := 2 U_wall - adjacent interior (interior extent of the
+// other two indices), then periodic images axis by axis (full extent).  The
+// three phases are separate launches so that every read sees the previous
+// phase's writes.
+
+// Face loop helper: thread (a, b) of a face of axis `ax`, a on the faster
+// of the two other axes.
+template <class T>
+__global__ void k_bc_normal(T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, Geo g) {
+  const int ax = blockIdx.z;
+  if (g.per[ax]) return;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y * blockDim.y + threadIdx.y;
+  if (ax == 0) {  // u faces 0 and nx; (a, b) = (j, k)
+    if (a > g.ny + 1 || b > g.nz + 1) return;
+    long base = (long)b * g.sxy + (long)a * g.sx;
+    u[base] = T(0);
+    u[base + g.nx] = T(0);
+  } else if (ax == 1) {  // v faces 0 and ny; (a, b) = (i, k)
+    if (a > g.nx + 1 || b > g.nz + 1) return;
+    long base = (long)b * g.sxy + a;
+    v[base] = T(0);
+    v[base + (long)g.ny * g.sx] = T(0);
+  } else {  // w faces 0 and nz; (a, b) = (i, j)
+    if (a > g.nx + 1 || b > g.ny + 1) return;
+    long base = (long)b * g.sx + a;
+    w[base] = T(0);
+    w[base + (long)g.nz * g.sxy] = T(0);
+  }
+}
+
+struct Wall {
+  double v[6][3];
+};
+
+template <class T>
+__global__ void k_bc_reflect(T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, Geo g,
+                             Wall wl) {
+  const int ax = blockIdx.z;
+  if (g.per[ax]) return;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  const int b = blockIdx.y * blockDim.y + threadIdx.y + 1;
+  if (ax == 0) {  // x walls: v and w ghosts at i = 0, nx+1; (a, b) = (j, k)
+    if (a > g.ny || b > g.nz) return;
+    long base = (long)b * g.sxy + (long)a * g.sx;
+    v[base] = T(2.0 * wl.v[0][1] - (double)v[base + 1]);
+    w[base] = T(2.0 * wl.v[0][2] - (double)w[base + 1]);
+    v[base + g.nx + 1] = T(2.0 * wl.v[1][1] - (double)v[base + g.nx]);
+    w[base + g.nx + 1] = T(2.0 * wl.v[1][2] - (double)w[base + g.nx]);
+  } else if (ax == 1) {  // y walls: u and w ghosts at j = 0, ny+1; (a, b) = (i, k)
+    if (a > g.nx || b > g.nz) return;
+    long base = (long)b * g.sxy + a;
+    long top = base + (long)(g.ny + 1) * g.sx;
+    u[base] = T(2.0 * wl.v[2][0] - (double)u[base + g.sx]);
+    w[base] = T(2.0 * wl.v[2][2] - (double)w[base + g.sx]);
+    u[top] = T(2.0 * wl.v[3][0] - (double)u[top - g.sx]);
+    w[top] = T(2.0 * wl.v[3][2] - (double)w[top - g.sx]);
+  } else {  // z walls: u and v ghosts at k = 0, nz+1; (a, b) = (i, j)
+    if (a > g.nx || b > g.ny) return;
+    long base = (long)b * g.sx + a;
+    long top = base + (long)(g.nz + 1) * g.sxy;
+    u[base] = T(2.0 * wl.v[4][0] - (double)u[base + g.sxy]);
+    v[base] = T(2.0 * wl.v[4][1] - (double)v[base + g.sxy]);
+    u[top] = T(2.0 * wl.v[5][0] - (double)u[top - g.sxy]);
+    v[top] = T(2.0 * wl.v[5][1] - (double)v[top - g.sxy]);
+  }
+}
+
+// Periodic images along one axis over the full extent of the other two;
+// up to three fields per launch (null pointers skipped).
+template <class T>
+__global__ void k_periodic(T* __restrict__ q0, T* __restrict__ q1, T* __restrict__ q2, Geo g,
+                           int ax) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y * blockDim.y + threadIdx.y;
+  long lo, hi, src_lo, src_hi;
+  if (ax == 0) {
+    if (a > g.ny + 1 || b > g.nz + 1) return;
+    long base = (long)b * g.sxy + (long)a * g.sx;
+    lo = base; hi = base + g.nx + 1; src_lo = base + g.nx; src_hi = base + 1;
+  } else if (ax == 1) {
+    if (a > g.nx + 1 || b > g.nz + 1) return;
+    long base = (long)b * g.sxy + a;
+    lo = base; hi = base + (long)(g.ny + 1) * g.sx;
+    src_lo = base + (long)g.ny * g.sx; src_hi = base + g.sx;
+  } else {
+    if (a > g.nx + 1 || b > g.ny + 1) return;
+    long base = (long)b * g.sx + a;
+    lo = base; hi = base + (long)(g.nz + 1) * g.sxy;
+    src_lo = base + (long)g.nz * g.sxy; src_hi = base + g.sxy;
+  }
+  T* q[3] = {q0, q1, q2};
+#pragma unroll
+  for (int f = 0; f < 3; f++)
+    if (q[f]) {
+      T a0 = q[f][src_lo], a1 = q[f][src_hi];
+      q[f][lo] = a0;
+      q[f][hi] = a1;
+    }
+}
+
+// Pressure ghosts on wall axes: Neumann copy of the adjacent cell.
+template <class T>
+__global__ void k_p_neumann(T* __restrict__ p, Geo g) {
+  const int ax = blockIdx.z;
+  if (g.per[ax]) return;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  const int b = blockIdx.y * blockDim.y + threadIdx.y + 1;
+  if (ax == 0) {
+    if (a > g.ny || b > g.nz) return;
+    long base = (long)b * g.sxy + (long)a * g.sx;
+    p[base] = p[base + 1];
+    p[base + g.nx + 1] = p[base + g.nx];
+  } else if (ax == 1) {
+    if (a > g.nx || b > g.nz) return;
+    long base = (long)b * g.sxy + a;
+    p[base] = p[base + g.sx];
+    p[base + (long)(g.ny + 1) * g.sx] = p[base + (long)g.ny * g.sx];
+  } else {
+    if (a > g.nx || b > g.ny) return;
+    long base = (long)b * g.sx + a;
+    p[base] = p[base + g.sxy];
+    p[base + (long)(g.nz + 1) * g.sxy] = p[base + (long)g.nz * g.sxy];
+  }
+}
+
+dim3 face_grid(const Geo& g, dim3 blk, int zdim) {
+  int m = g.nx > g.ny ? g.nx : g.ny;
+  m = m > g.nz ? m : g.nz;
+  m += 2;
+  return dim3((m + blk.x - 1) / blk.x, (m + blk.y - 1) / blk.y, zdim);
+}
+
+// ---------------------------------------------------------------------------
+// Momentum predictor.  For the unknown q of component c and direction d the
+// convective flux through the half-way point between q and q[+d] blends
+// central and donor-cell differencing:
+//     flux(t, a, b) = t (a + b)/2 + gamma |t| (a - b)/2,
+// t = the d-velocity interpolated to that point (mean of the two d-faces at
+// pos and pos + e_c; for d == c the mean of q and q[+d]).
+// F_c = q + dt (nu lap q - sum_d (flux_hi - flux_lo)/h_d + g_c + f_c).
+__device__ __forceinline__ double flux(double t, double a, double b, double gamma) {
+  return 0.5 * (t * (a + b) + gamma * fabs(t) * (a - b));
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_fgh(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
+      const T* __restrict__ fx, const T* __restrict__ fy, const T* __restrict__ fz,
+      T* __restrict__ F, T* __restrict__ G, T* __restrict__ H, Geo g, const Ctl* __restrict__ ctl,
+      double nu, double gamma, double gx, double gy, double gz) {
+  const double dt = ctl->dt;
+  const long n = (long)g.nx * g.ny * g.nz;
+  const long sx = g.sx, sxy = g.sxy;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const Cell cl = cell_of(g, t);
+    const long c = cl.c;
+    if (cl.i <= g.hi[0]) {  // F on the x face i
+      const double q = u[c], qe = u[c + 1], qw = u[c - 1], qn = u[c + sx], qs = u[c - sx],
+                   qt = u[c + sxy], qb = u[c - sxy];
+      const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
+                         (qt - 2.0 * q + qb) * g.idz2;
+      const double cx = (flux(0.5 * (q + qe), q, qe, gamma) - flux(0.5 * (qw + q), qw, q, gamma)) * g.idx;
+      const double vn = 0.5 * ((double)v[c] + (double)v[c + 1]);
+      const double vs = 0.5 * ((double)v[c - sx] + (double)v[c - sx + 1]);
+      const double cy = (flux(vn, q, qn, gamma) - flux(vs, qs, q, gamma)) * g.idy;
+      const double wt = 0.5 * ((double)w[c] + (double)w[c + 1]);
+      const double wb = 0.5 * ((double)w[c - sxy] + (double)w[c - sxy + 1]);
+      const double cz = (flux(wt, q, qt, gamma) - flux(wb, qb, q, gamma)) * g.idz;
+      const double f = gx + (fx ? (double)fx[c] : 0.0);
+      F[c] = T(q + dt * (nu * lap - cx - cy - cz + f));
+    }
+    if (cl.j <= g.hi[1]) {  // G on the y face j
+      const double q = v[c], qe = v[c + 1], qw = v[c - 1], qn = v[c + sx], qs = v[c - sx],
+                   qt = v[c + sxy], qb = v[c - sxy];
+      const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
+                         (qt - 2.0 * q + qb) * g.idz2;
+      const double ue = 0.5 * ((double)u[c] + (double)u[c + sx]);
+      const double uw = 0.5 * ((double)u[c - 1] + (double)u[c - 1 + sx]);
+      const double cx = (flux(ue, q, qe, gamma) - flux(uw, qw, q, gamma)) * g.idx;
+      const double cy = (flux(0.5 * (q + qn), q, qn, gamma) - flux(0.5 * (qs + q), qs, q, gamma)) * g.idy;
+      const double wt = 0.5 * ((double)w[c] + (double)w[c + sx]);
+      const double wb = 0.5 * ((double)w[c - sxy] + (double)w[c - sxy + sx]);
+      const double cz = (flux(wt, q, qt, gamma) - flux(wb, qb, q, gamma)) * g.idz;
+      const double f = gy + (fy ? (double)fy[c] : 0.0);
+      G[c] = T(q + dt * (nu * lap - cx - cy - cz + f));
+    }
+    if (cl.k <= g.hi[2]) {  // H on the z face k
+      const double q = w[c], qe = w[c + 1], qw = w[c - 1], qn = w[c + sx], qs = w[c - sx],
+                   qt = w[c + sxy], qb = w[c - sxy];
+      const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
+                         (qt - 2.0 * q + qb) * g.idz2;
+      const double ue = 0.5 * ((double)u[c] + (double)u[c + sxy]);
+      const double uw = 0.5 * ((double)u[c - 1] + (double)u[c - 1 + sxy]);
+      const double cx = (flux(ue, q, qe, gamma) - flux(uw, qw, q, gamma)) * g.idx;
+      const double vn = 0.5 * ((double)v[c] + (double)v[c + sxy]);
+      const double vs = 0.5 * ((double)v[c - sx] + (double)v[c - sx + sxy]);
+      const double cy = (flux(vn, q, qn, gamma) - flux(vs, qs, q, gamma)) * g.idy;
+      const double cz = (flux(0.5 * (q + qt), q, qt, gamma) - flux(0.5 * (qb + q), qb, q, gamma)) * g.idz;
+      const double f = gz + (fz ? (double)fz[c] : 0.0);
+      H[c] = T(q + dt * (nu * lap - cx - cy - cz + f));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Poisson right-hand side rhs = (div F) / dt on every cell (the face below
+// cell 1 of a periodic axis is face n), with the RMS of rhs reduced into the
+// control block: thr = tol * max(RMS, 1e-300); an identically zero rhs
+// finishes the solve before any sweep.  dt_scale_one != 0 uses dt = 1 (the
+// adjoint projection).
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_rhs(const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
+      T* __restrict__ rhs, Geo g, Ctl* ctl, double* part, double tol, int unit_dt) {
+  __shared__ double sh[16];
+  __shared__ int sh_last;
+  const double idt = unit_dt ? 1.0 : 1.0 / ctl->dt;
+  const long n = (long)g.nx * g.ny * g.nz;
+  double acc = 0.0;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const Cell cl = cell_of(g, t);
+    const long c = cl.c;
+    const long cw = (cl.i > 1 || !g.per[0]) ? c - 1 : c + (g.nx - 1);
+    const long cs = (cl.j > 1 || !g.per[1]) ? c - g.sx : c + (long)(g.ny - 1) * g.sx;
+    const long cb = (cl.k > 1 || !g.per[2]) ? c - g.sxy : c + (long)(g.nz - 1) * g.sxy;
+    const double d = ((double)F[c] - (double)F[cw]) * g.idx + ((double)G[c] - (double)G[cs]) * g.idy +
+                     ((double)H[c] - (double)H[cb]) * g.idz;
+    const T r = T(d * idt);
+    rhs[c] = r;
+    acc += (double)r * (double)r;
+  }
+  double s = block_sum(acc, sh);
+  if (publish_partial(part, blockIdx.x, s, ctl, gridDim.x, &sh_last)) {
+    double tot = sum_partials(part, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      const double rms = sqrt(tot / (double)n);
+      ctl->rhs_rms = rms;
+      ctl->thr = tol * (rms > 1e-300 ? rms : 1e-300);
+      ctl->res = 0.0;
+      ctl->final_ = 0;
+      ctl->nonfinite = !isfinite(rms);
+      ctl->done = (rms == 0.0) || !isfinite(rms);
+      ctl->outer_done = ctl->done;
+      ctl->ticket = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Projection (UPDATE_VELOCITY): u = F - dt (p[+x] - p) / dx on the unknowns
+// of each component; p ghosts hold periodic images where needed.
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_project(const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
+          const double* __restrict__ p, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w,
+          Geo g, const Ctl* __restrict__ ctl, int unit_dt) {
+  const double dt = unit_dt ? 1.0 : ctl->dt;
+  const long n = (long)g.nx * g.ny * g.nz;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const Cell cl = cell_of(g, t);
+    const long c = cl.c;
+    const double pc = p[c];
+    if (cl.i <= g.hi[0]) u[c] = T((double)F[c] - dt * (p[c + 1] - pc) * g.idx);
+    if (cl.j <= g.hi[1]) v[c] = T((double)G[c] - dt * (p[c + g.sx] - pc) * g.idy);
+    if (cl.k <= g.hi[2]) w[c] = T((double)H[c] - dt * (p[c + g.sxy] - pc) * g.idz);
+  }
+}
+
+// Adaptive step: tau * min(diffusive limit, h_d / max|u_d|) with the maxima
+// over the unknowns and the wall speeds.
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_umax(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w, Geo g, Ctl* ctl,
+       double* part, double re, double tau, double wu, double wv, double ww) {
+  __shared__ double sh[16];
+  __shared__ int sh_last;
+  const long n = (long)g.nx * g.ny * g.nz;
+  double m[3] = {0.0, 0.0, 0.0};
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const Cell cl = cell_of(g, t);
+    if (cl.i <= g.hi[0]) m[0] = fmax(m[0], fabs((double)u[cl.c]));
+    if (cl.j <= g.hi[1]) m[1] = fmax(m[1], fabs((double)v[cl.c]));
+    if (cl.k <= g.hi[2]) m[2] = fmax(m[2], fabs((double)w[cl.c]));
+  }
+  double r[3];
+  for (int d = 0; d < 3; d++) r[d] = block_max(m[d], sh);
+  const unsigned nb = gridDim.x;
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = r[0];
+    part[nb + blockIdx.x] = r[1];
+    part[2 * nb + blockIdx.x] = r[2];
+  }
+  if (publish_partial(part + 3 * nb, blockIdx.x, 0.0, ctl, nb, &sh_last)) {
+    double mm[3];
+    for (int d = 0; d < 3; d++) mm[d] = max_partials(part + d * nb, nb, sh);
+    if (threadIdx.x == 0) {
+      const double wall[3] = {wu, wv, ww};
+      const double h[3] = {g.dx, g.dy, g.dz};
+      double lim = (re / 2.0) / (g.idx2 + g.idy2 + g.idz2);
+      for (int d = 0; d < 3; d++) {
+        const double md = fmax(mm[d], wall[d]);
+        ctl->umax[d] = md;
+        if (md > 0.0) lim = fmin(lim, h[d] / md);
+      }
+      ctl->dt = tau * lim;
+      ctl->ticket = 0;
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_divergence(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
+             T* __restrict__ out, Geo g) {
+  const long n = (long)g.nx * g.ny * g.nz;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const Cell cl = cell_of(g, t);
+    const long c = cl.c;
+    out[c] = T(((double)u[c] - (double)u[c - 1]) * g.idx + ((double)v[c] - (double)v[c - g.sx]) * g.idy +
+               ((double)w[c] - (double)w[c - g.sxy]) * g.idz);
+  }
+}
+
+__global__ void k_mask(double* __restrict__ q, Geo g, int comp) {
+  const long n = g.ntot;
+  int hi[3] = {g.nx, g.ny, g.nz};
+  if (comp < 3) hi[comp] = g.hi[comp];
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const long k = t / g.sxy;
+    const long rem = t - k * g.sxy;
+    const long j = rem / g.sx;
+    const long i = rem - j * g.sx;
+    if (i < 1 || i > hi[0] || j < 1 || j > hi[1] || k < 1 || k > hi[2]) q[t] = 0.0;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+
+template <class T>
+hipError_t launch_bc_vel(hipStream_t st, const Geo& g, T* u, T* v, T* w, const double wall[6][3]) {
+  dim3 blk(64, 4);
+  dim3 grd = face_grid(g, blk, 3);
+  if (!(g.per[0] && g.per[1] && g.per[2])) {
+    Wall wl;
+    for (int f = 0; f < 6; f++)
+      for (int c = 0; c < 3; c++) wl.v[f][c] = wall[f][c];
+    k_bc_normal<T><<<grd, blk, 0, st>>>(u, v, w, g);
+    k_bc_reflect<T><<<grd, blk, 0, st>>>(u, v, w, g, wl);
+  }
+  for (int ax = 0; ax < 3; ax++)
+    if (g.per[ax]) k_periodic<T><<<face_grid(g, blk, 1), blk, 0, st>>>(u, v, w, g, ax);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_p_ghosts(hipStream_t st, const Geo& g, T* p) {
+  dim3 blk(64, 4);
+  if (!(g.per[0] && g.per[1] && g.per[2])) k_p_neumann<T><<<face_grid(g, blk, 3), blk, 0, st>>>(p, g);
+  for (int ax = 0; ax < 3; ax++)
+    if (g.per[ax]) k_periodic<T><<<face_grid(g, blk, 1), blk, 0, st>>>(p, nullptr, nullptr, g, ax);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_periodic(hipStream_t st, const Geo& g, T* q, int axis) {
+  dim3 blk(64, 4);
+  k_periodic<T><<<face_grid(g, blk, 1), blk, 0, st>>>(q, nullptr, nullptr, g, axis);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fgh(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, const T* fx,
+                      const T* fy, const T* fz, T* F, T* G, T* H, const Ctl* ctl, double re,
+                      double gamma, const double gf[3]) {
+  long n = (long)g.nx * g.ny * g.nz;
+  k_fgh<T><<<grid_for(n, 1 << 16), kBlock, 0, st>>>(u, v, w, fx, fy, fz, F, G, H, g, ctl, 1.0 / re,
+                                                     gamma, gf[0], gf[1], gf[2]);
+  return hipGetLastError();
+}
+
+size_t reduce_blocks(const Geo& g) {
+  long n = (long)g.nx * g.ny * g.nz;
+  size_t b = (size_t)grid_for(n);
+  size_t s = (size_t)sor_num_blocks(g, SorShape{8, 0});
+  size_t m = b > s ? b : s;
+  return 4 * m + 64 + 65536;
+}
+
+template <class T>
+hipError_t launch_rhs(hipStream_t st, const Geo& g, const T* F, const T* G, const T* H, T* rhs,
+                      Ctl* ctl, double* part, double tol, double unit_dt) {
+  long n = (long)g.nx * g.ny * g.nz;
+  k_rhs<T><<<grid_for(n), kBlock, 0, st>>>(F, G, H, rhs, g, ctl, part, tol, unit_dt != 0.0);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_project(hipStream_t st, const Geo& g, const T* F, const T* G, const T* H,
+                          const double* p, T* u, T* v, T* w, const Ctl* ctl, double unit_dt) {
+  long n = (long)g.nx * g.ny * g.nz;
+  k_project<T><<<grid_for(n, 1 << 16), kBlock, 0, st>>>(F, G, H, p, u, v, w, g, ctl, unit_dt != 0.0);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_umax(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, Ctl* ctl,
+                       double* part, double re, double tau, const double wall[6][3]) {
+  long n = (long)g.nx * g.ny * g.nz;
+  double wm[3] = {0, 0, 0};
+  for (int f = 0; f < 6; f++)
+    for (int c = 0; c < 3; c++) wm[c] = fmax(wm[c], fabs(wall[f][c]));
+  k_umax<T><<<grid_for(n), kBlock, 0, st>>>(u, v, w, g, ctl, part, re, tau, wm[0], wm[1], wm[2]);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_divergence(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, T* out) {
+  long n = (long)g.nx * g.ny * g.nz;
+  k_divergence<T><<<grid_for(n, 1 << 16), kBlock, 0, st>>>(u, v, w, out, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_unknowns(hipStream_t st, const Geo& g, double* q, int comp) {
+  k_mask<<<grid_for(g.ntot, 1 << 16), kBlock, 0, st>>>(q, g, comp);
+  return hipGetLastError();
+}
+
+#define NS_INST(T)                                                                                  \
+  template hipError_t launch_bc_vel<T>(hipStream_t, const Geo&, T*, T*, T*, const double[6][3]);    \
+  template hipError_t launch_p_ghosts<T>(hipStream_t, const Geo&, T*);                              \
+  template hipError_t launch_periodic<T>(hipStream_t, const Geo&, T*, int);                         \
+  template hipError_t launch_fgh<T>(hipStream_t, const Geo&, const T*, const T*, const T*,          \
+                                    const T*, const T*, const T*, T*, T*, T*, const Ctl*, double,   \
+                                    double, const double[3]);                                       \
+  template hipError_t launch_rhs<T>(hipStream_t, const Geo&, const T*, const T*, const T*, T*,      \
+                                    Ctl*, double*, double, double);                                 \
+  template hipError_t launch_project<T>(hipStream_t, const Geo&, const T*, const T*, const T*,      \
+                                        const double*, T*, T*, T*, const Ctl*, double);             \
+  template hipError_t launch_umax<T>(hipStream_t, const Geo&, const T*, const T*, const T*, Ctl*,   \
+                                     double*, double, double, const double[6][3]);                  \
+  template hipError_t launch_divergence<T>(hipStream_t, const Geo&, const T*, const T*, const T*, T*);
+
+NS_INST(double)
+NS_INST(float)
+
+}  // namespace ns

@@ -1,0 +1,805 @@
+// runtime.hip -- host runtime and C ABI of libns.so (see include/ns.h).
+//
+// One handle owns one HIP stream (the caller's) and, per instance, every
+// device buffer of the step.  A step enqueues its stage kernels on that
+// stream; the Poisson solve enqueues red-black sweeps in chunks and, after
+// each chunk, reads the instance's 128-byte control block back (the only
+// device-to-host traffic inside a step).  Sweeps launched after the stop
+// rule fired return at once on the device flag.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ns.h"
+#include "ns_internal.h"
+
+using namespace ns;
+
+namespace {
+
+thread_local std::string g_create_err = "no error";
+
+struct State {
+  void* u = nullptr;
+  void* v = nullptr;
+  void* w = nullptr;
+  double* p[2] = {nullptr, nullptr};
+  int pcur = 0;
+};
+
+struct Inst {
+  ns_params prm{};
+  Geo g{};
+  bool mixed = false;
+  size_t esz = 8;      // bytes per element of u, v, w, F, G, H, rhs, forces
+  size_t bytes = 0;    // ntot * esz
+  size_t pbytes = 0;   // ntot * 8
+  State s;
+  void* F = nullptr;
+  void* G = nullptr;
+  void* H = nullptr;
+  void* rhs = nullptr;
+  void* frc[3] = {nullptr, nullptr, nullptr};
+  float* e[2] = {nullptr, nullptr};
+  float* r = nullptr;
+  double* part = nullptr;
+  Ctl* ctl = nullptr;
+  ns_stats st{};
+  int pred = 0;
+  SorShape shape{8, 0};
+  // adjoint recording (FP64)
+  std::vector<State> ck;
+  int rec_steps = 0;
+  bool rec_valid = false;
+  // adjoint work (lazily allocated)
+  State R;
+  double* lam[3] = {nullptr, nullptr, nullptr};
+  double* z[3] = {nullptr, nullptr, nullptr};
+  double* q[2] = {nullptr, nullptr};
+  int qcur = 0;
+  std::vector<double*> hist;
+};
+
+struct EvRec {
+  hipEvent_t a, b;
+  int stage;
+  int m;            // sweep index (SOR) or 0
+  long long bytes;  // algorithmic bytes of the launch
+};
+
+}  // namespace
+
+struct ns_solver {
+  std::vector<Inst> in;
+  hipStream_t stream = nullptr;
+  Ctl* hctl = nullptr;  // pinned host mirror, one per instance
+  std::string err = "no error";
+  int device = 0;
+  bool timing = false;
+  ns_timing tm{};
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  std::vector<EvRec> recs;
+  double* stage = nullptr;  // FP64 staging buffer for conversions
+  size_t stage_n = 0;
+};
+
+namespace {
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DevGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+ns_status fail(ns_solver* s, ns_status code, const std::string& msg) {
+  if (s) s->err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+ns_status fail_hip(ns_solver* s, const char* what, hipError_t e) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(s, e == hipErrorOutOfMemory ? NS_E_OOM : NS_E_DEVICE, m);
+}
+
+#define HCK(s, x)                                      \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) return fail_hip((s), #x, e_); \
+  } while (0)
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+__global__ void k_to_f64(const float* __restrict__ a, double* __restrict__ b, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    b[i] = (double)a[i];
+}
+int conv_grid(long n) {
+  long b = (n + 255) / 256;
+  return (int)std::min<long>(std::max<long>(b, 1), 16384);
+}
+
+Geo make_geo(const ns_params& p) {
+  Geo g{};
+  g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
+  g.sx = p.nx + 2;
+  g.sxy = g.sx * (long)(p.ny + 2);
+  g.ntot = g.sxy * (long)(p.nz + 2);
+  g.dx = p.lx / p.nx; g.dy = p.ly / p.ny; g.dz = p.lz / p.nz;
+  g.idx = 1.0 / g.dx; g.idy = 1.0 / g.dy; g.idz = 1.0 / g.dz;
+  g.idx2 = g.idx * g.idx; g.idy2 = g.idy * g.idy; g.idz2 = g.idz * g.idz;
+  for (int a = 0; a < 3; a++) g.per[a] = p.bc[a] == NS_BC_PERIODIC;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  for (int a = 0; a < 3; a++) g.hi[a] = g.per[a] ? n[a] : n[a] - 1;
+  return g;
+}
+
+ns_status validate(const ns_params& p, int idx) {
+  char b[256];
+  auto bad = [&](const char* what) {
+    snprintf(b, sizeof b, "instance %d: %s", idx, what);
+    return fail(nullptr, NS_E_INVALID, b);
+  };
+  if (p.struct_size != sizeof(ns_params)) return bad("struct_size != sizeof(ns_params)");
+  const int n[3] = {p.nx, p.ny, p.nz};
+  for (int a = 0; a < 3; a++) {
+    if (n[a] < 2) return bad("every axis needs at least 2 cells");
+    if (n[a] > 32768) return bad("axis longer than 32768 cells");
+    if (p.bc[a] != NS_BC_WALL && p.bc[a] != NS_BC_PERIODIC) return bad("bc must be wall or periodic");
+    if (p.bc[a] == NS_BC_PERIODIC && (n[a] & 1)) return bad("periodic axes need an even cell count");
+  }
+  if ((double)(p.nx + 2) * (p.ny + 2) * (p.nz + 2) > 4.0e9) return bad("grid too large");
+  if (!(p.lx > 0 && p.ly > 0 && p.lz > 0)) return bad("domain extents must be positive");
+  if (!(p.re > 0) || !std::isfinite(p.re)) return bad("re must be positive");
+  if (!std::isfinite(p.dt)) return bad("dt must be finite");
+  if (p.dt <= 0 && !(p.tau > 0 && p.tau <= 1)) return bad("adaptive dt needs tau in (0, 1]");
+  if (!(p.gamma >= 0 && p.gamma <= 1)) return bad("gamma must lie in [0, 1]");
+  if (!(p.omega > 0 && p.omega < 2)) return bad("omega must lie in (0, 2)");
+  if (!(p.tol >= 0) || !std::isfinite(p.tol)) return bad("tol must be >= 0");
+  if (p.itermax < 0) return bad("itermax must be >= 0");
+  if (p.precision != NS_FP64 && p.precision != NS_MIXED) return bad("precision must be NS_FP64 or NS_MIXED");
+  if (p.precision == NS_MIXED && !(p.eta > 0 && p.eta < 1)) return bad("mixed precision needs eta in (0, 1)");
+  if (p.checkpoint_every < 0) return bad("checkpoint_every must be >= 0");
+  if (p.checkpoint_every > 0 && (p.precision != NS_FP64 || p.dt <= 0))
+    return bad("recording for ns_backward needs NS_FP64 and a fixed dt");
+  for (int f = 0; f < 6; f++)
+    for (int c = 0; c < 3; c++)
+      if (!std::isfinite(p.wall_vel[f][c])) return bad("wall velocities must be finite");
+  for (int c = 0; c < 3; c++)
+    if (!std::isfinite(p.g[c])) return bad("body force must be finite");
+  if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING)) return bad("unknown flag bits");
+  if (p.dt > 0 && !(p.flags & NS_ALLOW_UNSTABLE)) {
+    const double dx = p.lx / p.nx, dy = p.ly / p.ny, dz = p.lz / p.nz;
+    const double diff = p.dt / p.re * (1 / (dx * dx) + 1 / (dy * dy) + 1 / (dz * dz));
+    double wmax = 0;
+    for (int f = 0; f < 6; f++)
+      for (int c = 0; c < 3; c++) wmax = std::max(wmax, std::fabs(p.wall_vel[f][c]));
+    const double cfl = wmax * p.dt / std::min(dx, std::min(dy, dz));
+    if (diff > 0.5 || cfl > 1.0) {
+      snprintf(b, sizeof b,
+               "instance %d: dt = %g exceeds the explicit bounds (diffusion number %.3g > 0.5 or "
+               "wall CFL %.3g > 1); set NS_ALLOW_UNSTABLE to run anyway",
+               idx, p.dt, diff, cfl);
+      return fail(nullptr, NS_E_UNSTABLE, b);
+    }
+  }
+  return NS_OK;
+}
+
+hipError_t dmalloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) { *p = nullptr; return e; }
+  return hipMemset(*p, 0, bytes);
+}
+
+void free_state(State& s) {
+  hipFree(s.u); hipFree(s.v); hipFree(s.w);
+  hipFree(s.p[0]); hipFree(s.p[1]);
+  s = State{};
+}
+
+void free_inst(Inst& I) {
+  free_state(I.s);
+  hipFree(I.F); hipFree(I.G); hipFree(I.H); hipFree(I.rhs);
+  for (int c = 0; c < 3; c++) hipFree(I.frc[c]);
+  hipFree(I.e[0]); hipFree(I.e[1]); hipFree(I.r);
+  hipFree(I.part); hipFree(I.ctl);
+  for (auto& c : I.ck) free_state(c);
+  I.ck.clear();
+  free_state(I.R);
+  for (int c = 0; c < 3; c++) { hipFree(I.lam[c]); hipFree(I.z[c]); }
+  hipFree(I.q[0]); hipFree(I.q[1]);
+  for (auto* h : I.hist) hipFree(h);
+  I.hist.clear();
+}
+
+hipError_t alloc_state(State& S, const Inst& I) {
+  hipError_t e;
+  if ((e = dmalloc(&S.u, I.bytes)) != hipSuccess) return e;
+  if ((e = dmalloc(&S.v, I.bytes)) != hipSuccess) return e;
+  if ((e = dmalloc(&S.w, I.bytes)) != hipSuccess) return e;
+  if ((e = dmalloc((void**)&S.p[0], I.pbytes)) != hipSuccess) return e;
+  if ((e = dmalloc((void**)&S.p[1], I.pbytes)) != hipSuccess) return e;
+  S.pcur = 0;
+  return hipSuccess;
+}
+
+// ---- timing ----------------------------------------------------------------
+struct Timed {
+  ns_solver* s;
+  bool on;
+  size_t idx;
+  Timed(ns_solver* s_, int stage, int m = 0, long long bytes = 0) : s(s_), on(s_->timing), idx(0) {
+    if (!on) return;
+    if (s->pool_used + 2 > s->pool.size()) {
+      for (int i = 0; i < 64; i++) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+        s->pool.push_back(e);
+      }
+    }
+    EvRec r{s->pool[s->pool_used], s->pool[s->pool_used + 1], stage, m, bytes};
+    s->pool_used += 2;
+    (void)hipEventRecord(r.a, s->stream);
+    idx = s->recs.size();
+    s->recs.push_back(r);
+  }
+  ~Timed() {
+    if (on) (void)hipEventRecord(s->recs[idx].b, s->stream);
+  }
+};
+
+// After a synchronised step: fold recorded launches into the totals.  SOR
+// launches with sweep index above `last_real` returned on the done flag and
+// are not counted.
+void harvest(ns_solver* s, int last_real) {
+  if (!s->timing) return;
+  for (auto& r : s->recs) {
+    if (r.stage == NS_T_COUNT - 1) continue;  // returned on the done flag
+    if (r.stage == NS_T_SOR && r.m < 1000000 && r.m > last_real) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+    s->tm.ms[r.stage] += ms;
+    s->tm.launches[r.stage] += 1;
+    if (r.stage == NS_T_SOR) s->tm.sor_bytes += r.bytes;
+  }
+  s->recs.clear();
+  s->pool_used = 0;
+}
+
+ns_status poll(ns_solver* s, int idx) {
+  Inst& I = s->in[idx];
+  HCK(s, hipMemcpyAsync(&s->hctl[idx], I.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+  HCK(s, hipStreamSynchronize(s->stream));
+  return NS_OK;
+}
+
+// ---- Poisson solves ----------------------------------------------------------
+// FP64 red-black SOR on A p = rhs from P[*cur]; on return *cur indexes the
+// accepted iterate, *sweeps its sweep count.
+ns_status solve_fp64(ns_solver* s, int idx, double* P[2], int* cur, int* sweeps) {
+  Inst& I = s->in[idx];
+  const int itermax = I.prm.itermax;
+  const long N = (long)I.g.nx * I.g.ny * I.g.nz;
+  int m = 0;
+  int pred = std::min(std::max(I.pred + 2, 4), itermax + 1);
+  bool first = true;
+  for (;;) {
+    int chunk = first ? pred : std::max(4, pred / 4);
+    first = false;
+    bool last_pass = false;
+    for (int c = 0; c < chunk; c++) {
+      m++;
+      if (m <= itermax) {
+        Timed t(s, NS_T_SOR, m, 24LL * N);
+        HCK(s, launch_sor_sweep<double>(s->stream, I.g, P[(*cur + m - 1) & 1], P[(*cur + m) & 1],
+                                        (const double*)I.rhs, I.ctl, I.part, I.prm.omega, m, itermax, 1,
+                                        0, 0, I.shape));
+      } else {
+        Timed t(s, NS_T_SOR, m, 16LL * N);
+        HCK(s, launch_sor_sweep<double>(s->stream, I.g, P[(*cur + itermax) & 1], nullptr,
+                                        (const double*)I.rhs, I.ctl, I.part, I.prm.omega, m, itermax, 0,
+                                        0, 0, I.shape));
+        last_pass = true;
+        break;
+      }
+    }
+    ns_status e = poll(s, idx);
+    if (e != NS_OK) return e;
+    if (s->hctl[idx].done || last_pass) break;
+  }
+  const Ctl& h = s->hctl[idx];
+  if (!h.done) return fail(s, NS_E_DEVICE, "Poisson solve ended without a decision");
+  *sweeps = h.final_;
+  *cur = (*cur + h.final_) & 1;
+  I.pred = h.final_;
+  return NS_OK;
+}
+
+// Mixed precision: FP64 outer defect correction around FP32 red-black
+// sweeps on A e = r.  P (FP64) ping-pongs once per outer iteration.
+ns_status solve_mixed(ns_solver* s, int idx, int* sweeps, int* outer) {
+  Inst& I = s->in[idx];
+  State& S = I.s;
+  const int itermax = I.prm.itermax;
+  const long N = (long)I.g.nx * I.g.ny * I.g.nz;
+  int used = 0;
+  *outer = 0;
+  {
+    Timed t(s, NS_T_DEFECT, 0, 20LL * N);
+    HCK(s, launch_defect(s->stream, I.g, S.p[S.pcur], nullptr, nullptr, (const float*)I.rhs, I.r, I.ctl,
+                         I.part, I.prm.eta));
+  }
+  for (;;) {
+    ns_status e = poll(s, idx);
+    if (e != NS_OK) return e;
+    const Ctl& h = s->hctl[idx];
+    if (h.outer_done || h.nonfinite || used >= itermax) break;
+    (*outer)++;
+    const int budget = itermax - used;
+    int m = 0;
+    int pred = std::min(std::max(I.pred + 2, 4), budget);
+    bool first = true;
+    int f = -1;
+    const size_t rec0 = s->recs.size();
+    for (;;) {
+      int chunk = first ? pred : std::max(4, pred / 4);
+      first = false;
+      for (int c = 0; c < chunk && m < budget; c++) {
+        m++;
+        Timed t(s, NS_T_SOR, 1000000 + m, (m == 1 ? 8LL : 12LL) * N);
+        HCK(s, launch_sor_sweep<float>(s->stream, I.g, I.e[(m - 1) & 1], I.e[m & 1], I.r, I.ctl, I.part,
+                                       I.prm.omega, m, itermax + 1, 1, m == 1, 1, I.shape));
+      }
+      e = poll(s, idx);
+      if (e != NS_OK) return e;
+      if (s->hctl[idx].done) { f = s->hctl[idx].final_; break; }
+      if (m >= budget) { f = budget; break; }
+    }
+    used += f;
+    I.pred = f;
+    // launches past the one that found convergence returned on the flag
+    for (size_t q = rec0; q < s->recs.size(); q++)
+      if (s->recs[q].stage == NS_T_SOR && s->recs[q].m - 1000000 > f + 1) s->recs[q].stage = NS_T_COUNT - 1;
+    Timed t(s, NS_T_DEFECT, 0, 40LL * N);
+    HCK(s, launch_defect(s->stream, I.g, S.p[S.pcur], I.e[f & 1], S.p[S.pcur ^ 1], (const float*)I.rhs, I.r,
+                         I.ctl, I.part, I.prm.eta));
+    S.pcur ^= 1;
+  }
+  *sweeps = used;
+  return NS_OK;
+}
+
+// ---- one step ------------------------------------------------------------------
+template <class T>
+ns_status step_inst(ns_solver* s, int idx, State& S, bool account) {
+  Inst& I = s->in[idx];
+  const Geo& g = I.g;
+  const ns_params& p = I.prm;
+  T* u = (T*)S.u;
+  T* v = (T*)S.v;
+  T* w = (T*)S.w;
+  if (p.dt <= 0) {
+    Timed t(s, NS_T_OTHER);
+    HCK(s, launch_umax<T>(s->stream, g, u, v, w, I.ctl, I.part, p.re, p.tau, p.wall_vel));
+  }
+  {
+    Timed t(s, NS_T_BC);
+    HCK(s, launch_bc_vel<T>(s->stream, g, u, v, w, p.wall_vel));
+  }
+  {
+    Timed t(s, NS_T_FGH);
+    HCK(s, launch_fgh<T>(s->stream, g, u, v, w, (const T*)I.frc[0], (const T*)I.frc[1], (const T*)I.frc[2],
+                         (T*)I.F, (T*)I.G, (T*)I.H, I.ctl, p.re, p.gamma, p.g));
+  }
+  {
+    Timed t(s, NS_T_RHS);
+    HCK(s, launch_rhs<T>(s->stream, g, (const T*)I.F, (const T*)I.G, (const T*)I.H, (T*)I.rhs, I.ctl, I.part,
+                         p.tol, 0.0));
+  }
+  int sweeps = 0, outer = 0;
+  ns_status e;
+  if (I.mixed) {
+    e = solve_mixed(s, idx, &sweeps, &outer);
+  } else {
+    e = solve_fp64(s, idx, S.p, &S.pcur, &sweeps);
+  }
+  if (e != NS_OK) return e;
+  const Ctl h = s->hctl[idx];
+  {
+    Timed t(s, NS_T_PROJECT);
+    HCK(s, launch_p_ghosts<double>(s->stream, g, S.p[S.pcur]));
+    HCK(s, launch_project<T>(s->stream, g, (const T*)I.F, (const T*)I.G, (const T*)I.H, S.p[S.pcur], u, v, w,
+                             I.ctl, 0.0));
+  }
+  {
+    Timed t(s, NS_T_BC);
+    HCK(s, launch_bc_vel<T>(s->stream, g, u, v, w, p.wall_vel));
+  }
+  if (s->timing) {
+    HCK(s, hipStreamSynchronize(s->stream));
+    harvest(s, I.mixed ? 1 << 30 : sweeps + 1);
+  }
+  if (h.nonfinite) return fail(s, NS_E_NONFINITE, "non-finite residual in the pressure solve");
+  if (account) {
+    ns_stats& st = I.st;
+    st.t += h.dt;
+    st.dt_last = h.dt;
+    st.res_last = h.res;
+    st.sweeps_total += sweeps;
+    st.sweeps_max = std::max(st.sweeps_max, sweeps);
+    st.outer_max = std::max(st.outer_max, outer);
+    if (h.res > h.thr) st.steps_unconverged++;
+    st.steps++;
+  }
+  return NS_OK;
+}
+
+ns_status copy_in(ns_solver* s, Inst& I, void* dst, bool dst_f32, const double* src, int on_device) {
+  const long n = I.g.ntot;
+  hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (!dst_f32) {
+    HCK(s, hipMemcpyAsync(dst, src, n * sizeof(double), kind, s->stream));
+  } else {
+    const double* from = src;
+    if (!on_device) {
+      HCK(s, hipMemcpyAsync(s->stage, src, n * sizeof(double), kind, s->stream));
+      from = s->stage;
+    }
+    k_to_f32<<<conv_grid(n), 256, 0, s->stream>>>(from, (float*)dst, n);
+    HCK(s, hipGetLastError());
+  }
+  HCK(s, hipStreamSynchronize(s->stream));
+  return NS_OK;
+}
+
+ns_status copy_out(ns_solver* s, const Inst& I, const void* src, bool src_f32, double* dst, int on_device) {
+  const long n = I.g.ntot;
+  hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (!src_f32) {
+    HCK(s, hipMemcpyAsync(dst, src, n * sizeof(double), kind, s->stream));
+  } else {
+    double* to = on_device ? dst : s->stage;
+    k_to_f64<<<conv_grid(n), 256, 0, s->stream>>>((const float*)src, to, n);
+    HCK(s, hipGetLastError());
+    if (!on_device) HCK(s, hipMemcpyAsync(dst, s->stage, n * sizeof(double), kind, s->stream));
+  }
+  HCK(s, hipStreamSynchronize(s->stream));
+  return NS_OK;
+}
+
+ns_status save_state(ns_solver* s, Inst& I, const State& from, State& to) {
+  HCK(s, hipMemcpyAsync(to.u, from.u, I.bytes, hipMemcpyDeviceToDevice, s->stream));
+  HCK(s, hipMemcpyAsync(to.v, from.v, I.bytes, hipMemcpyDeviceToDevice, s->stream));
+  HCK(s, hipMemcpyAsync(to.w, from.w, I.bytes, hipMemcpyDeviceToDevice, s->stream));
+  HCK(s, hipMemcpyAsync(to.p[0], from.p[from.pcur], I.pbytes, hipMemcpyDeviceToDevice, s->stream));
+  to.pcur = 0;
+  return NS_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+
+extern "C" {
+
+ns_status ns_params_default(ns_params* p) {
+  if (!p) return NS_E_INVALID;
+  memset(p, 0, sizeof *p);
+  p->struct_size = sizeof(ns_params);
+  p->nx = p->ny = p->nz = 16;
+  p->lx = p->ly = p->lz = 1.0;
+  p->re = 100.0;
+  p->dt = 0.01;
+  p->tau = 0.5;
+  p->gamma = 0.5;
+  p->omega = 1.7;
+  p->tol = 1e-6;
+  p->itermax = 200;
+  p->wall_vel[5][0] = 1.0;
+  p->eta = 1e-2;
+  p->precision = NS_FP64;
+  return NS_OK;
+}
+
+ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stream, ns_solver** out) {
+  if (!out) return fail(nullptr, NS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!params || n_instances < 1) return fail(nullptr, NS_E_INVALID, "need params[n_instances], n_instances >= 1");
+  for (int i = 0; i < n_instances; i++) {
+    ns_status st = validate(params[i], i);
+    if (st != NS_OK) return st;
+  }
+  ns_solver* s = new ns_solver();
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(nullptr, NS_E_DEVICE, "no HIP device");
+  }
+  s->stream = (hipStream_t)hip_stream;
+  s->in.resize(n_instances);
+  s->timing = (params[0].flags & NS_TIMING) != 0;
+  auto bail = [&](ns_status code, const std::string& m) {
+    g_create_err = m;
+    ns_destroy(s);
+    return code;
+  };
+  if (hipHostMalloc((void**)&s->hctl, sizeof(Ctl) * n_instances, hipHostMallocDefault) != hipSuccess)
+    return bail(NS_E_OOM, "pinned control block allocation failed");
+  memset(s->hctl, 0, sizeof(Ctl) * n_instances);
+  size_t max_ntot = 0;
+  for (int i = 0; i < n_instances; i++) {
+    Inst& I = s->in[i];
+    I.prm = params[i];
+    I.g = make_geo(I.prm);
+    I.mixed = I.prm.precision == NS_MIXED;
+    I.esz = I.mixed ? 4 : 8;
+    I.bytes = (size_t)I.g.ntot * I.esz;
+    I.pbytes = (size_t)I.g.ntot * 8;
+    max_ntot = std::max(max_ntot, (size_t)I.g.ntot);
+    hipError_t e = alloc_state(I.s, I);
+    if (e == hipSuccess) e = dmalloc(&I.F, I.bytes);
+    if (e == hipSuccess) e = dmalloc(&I.G, I.bytes);
+    if (e == hipSuccess) e = dmalloc(&I.H, I.bytes);
+    if (e == hipSuccess) e = dmalloc(&I.rhs, I.bytes);
+    if (e == hipSuccess && I.mixed) {
+      e = dmalloc((void**)&I.e[0], (size_t)I.g.ntot * 4);
+      if (e == hipSuccess) e = dmalloc((void**)&I.e[1], (size_t)I.g.ntot * 4);
+      if (e == hipSuccess) e = dmalloc((void**)&I.r, (size_t)I.g.ntot * 4);
+    }
+    if (e == hipSuccess) e = dmalloc((void**)&I.part, reduce_blocks(I.g) * sizeof(double));
+    if (e == hipSuccess) e = dmalloc((void**)&I.ctl, sizeof(Ctl));
+    if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? NS_E_OOM : NS_E_DEVICE,
+                                     std::string("allocation failed: ") + hipGetErrorString(e));
+    Ctl c{};
+    c.dt = I.prm.dt > 0 ? I.prm.dt : 0.0;
+    if (hipMemcpy(I.ctl, &c, sizeof c, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(NS_E_DEVICE, "control block upload failed");
+    I.rec_valid = I.prm.checkpoint_every > 0;
+  }
+  // staging buffer for FP32 conversions of host data
+  bool any_mixed = false;
+  for (auto& I : s->in) any_mixed |= I.mixed;
+  if (any_mixed) {
+    if (hipMalloc((void**)&s->stage, max_ntot * sizeof(double)) != hipSuccess)
+      return bail(NS_E_OOM, "staging buffer allocation failed");
+    s->stage_n = max_ntot;
+  }
+  for (int i = 0; i < n_instances; i++) {
+    Inst& I = s->in[i];
+    hipError_t e = I.mixed ? launch_bc_vel<float>(s->stream, I.g, (float*)I.s.u, (float*)I.s.v, (float*)I.s.w,
+                                                  I.prm.wall_vel)
+                           : launch_bc_vel<double>(s->stream, I.g, (double*)I.s.u, (double*)I.s.v,
+                                                   (double*)I.s.w, I.prm.wall_vel);
+    if (e != hipSuccess) return bail(NS_E_DEVICE, std::string("boundary fill failed: ") + hipGetErrorString(e));
+  }
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(NS_E_DEVICE, "stream synchronisation failed");
+  *out = s;
+  return NS_OK;
+}
+
+ns_status ns_set_state(ns_solver* s, int32_t inst, int32_t field, const double* src, int32_t on_device) {
+  if (!s) return fail(nullptr, NS_E_INVALID, "NULL handle");
+  if (inst < 0 || inst >= (int)s->in.size()) return fail(s, NS_E_INVALID, "instance out of range");
+  if (!src) return fail(s, NS_E_INVALID, "src is NULL");
+  DevGuard dg(s->device);
+  Inst& I = s->in[inst];
+  void* dst = nullptr;
+  bool f32 = I.mixed;
+  switch (field) {
+    case NS_U: dst = I.s.u; break;
+    case NS_V: dst = I.s.v; break;
+    case NS_W: dst = I.s.w; break;
+    case NS_P: dst = I.s.p[I.s.pcur]; f32 = false; break;
+    case NS_FX: case NS_FY: case NS_FZ: {
+      void*& f = I.frc[field - NS_FX];
+      if (!f) HCK(s, dmalloc(&f, I.bytes));
+      dst = f;
+      break;
+    }
+    case NS_F: dst = I.F; break;
+    case NS_G: dst = I.G; break;
+    case NS_H: dst = I.H; break;
+    case NS_RHS: dst = I.rhs; break;
+    default: return fail(s, NS_E_INVALID, "unknown field id");
+  }
+  ns_status e = copy_in(s, I, dst, f32, src, on_device);
+  if (e != NS_OK) return e;
+  if (field <= NS_P) {
+    I.rec_steps = 0;
+    I.rec_valid = I.prm.checkpoint_every > 0;
+  }
+  return NS_OK;
+}
+
+ns_status ns_get_state(const ns_solver* cs, int32_t inst, int32_t field, double* dst, int32_t on_device) {
+  ns_solver* s = const_cast<ns_solver*>(cs);
+  if (!s) return fail(nullptr, NS_E_INVALID, "NULL handle");
+  if (inst < 0 || inst >= (int)s->in.size()) return fail(s, NS_E_INVALID, "instance out of range");
+  if (!dst) return fail(s, NS_E_INVALID, "dst is NULL");
+  DevGuard dg(s->device);
+  const Inst& I = s->in[inst];
+  const void* src = nullptr;
+  bool f32 = I.mixed;
+  switch (field) {
+    case NS_U: src = I.s.u; break;
+    case NS_V: src = I.s.v; break;
+    case NS_W: src = I.s.w; break;
+    case NS_P: src = I.s.p[I.s.pcur]; f32 = false; break;
+    case NS_FX: case NS_FY: case NS_FZ:
+      src = I.frc[field - NS_FX];
+      if (!src) {  // never set: zero
+        if (on_device) HCK(s, hipMemsetAsync(dst, 0, I.g.ntot * sizeof(double), s->stream));
+        else memset(dst, 0, I.g.ntot * sizeof(double));
+        HCK(s, hipStreamSynchronize(s->stream));
+        return NS_OK;
+      }
+      break;
+    case NS_F: src = I.F; break;
+    case NS_G: src = I.G; break;
+    case NS_H: src = I.H; break;
+    case NS_RHS: src = I.rhs; break;
+    default: return fail(s, NS_E_INVALID, "unknown field id");
+  }
+  return copy_out(s, I, src, f32, dst, on_device);
+}
+
+ns_status ns_step(ns_solver* s, int32_t nsteps, ns_stats* stats) {
+  if (!s) return fail(nullptr, NS_E_INVALID, "NULL handle");
+  if (nsteps < 0) return fail(s, NS_E_INVALID, "nsteps must be >= 0");
+  DevGuard dg(s->device);
+  ns_status ret = NS_OK;
+  for (int n = 0; n < nsteps && ret == NS_OK; n++) {
+    for (int i = 0; i < (int)s->in.size() && ret == NS_OK; i++) {
+      Inst& I = s->in[i];
+      const int k = I.prm.checkpoint_every;
+      if (k > 0 && I.rec_valid && I.rec_steps % k == 0) {
+        const size_t slot = I.rec_steps / k;
+        while (I.ck.size() <= slot) {
+          I.ck.emplace_back();
+          hipError_t e = alloc_state(I.ck.back(), I);
+          if (e != hipSuccess) { ret = fail_hip(s, "checkpoint allocation", e); break; }
+        }
+        if (ret == NS_OK) ret = save_state(s, I, I.s, I.ck[slot]);
+      }
+      if (ret != NS_OK) break;
+      ret = I.mixed ? step_inst<float>(s, i, I.s, true) : step_inst<double>(s, i, I.s, true);
+      if (ret == NS_OK && k > 0 && I.rec_valid) I.rec_steps++;
+      if (ret != NS_OK) I.rec_valid = false;
+    }
+  }
+  if (stats)
+    for (size_t i = 0; i < s->in.size(); i++) stats[i] = s->in[i].st;
+  return ret;
+}
+
+ns_status ns_get_timing(const ns_solver* s, ns_timing* out) {
+  if (!s || !out) return fail(const_cast<ns_solver*>(s), NS_E_INVALID, "NULL argument");
+  *out = s->tm;
+  return NS_OK;
+}
+
+ns_status ns_backward(ns_solver* s, int32_t inst, const double* const g_final[3], double* const g_init[3],
+                      int32_t on_device) {
+  if (!s) return fail(nullptr, NS_E_INVALID, "NULL handle");
+  if (inst < 0 || inst >= (int)s->in.size()) return fail(s, NS_E_INVALID, "instance out of range");
+  if (!g_final || !g_init) return fail(s, NS_E_INVALID, "NULL gradient array");
+  for (int c = 0; c < 3; c++)
+    if (!g_final[c] || !g_init[c]) return fail(s, NS_E_INVALID, "NULL gradient field");
+  Inst& I = s->in[inst];
+  if (I.prm.checkpoint_every <= 0 || I.mixed || I.prm.dt <= 0)
+    return fail(s, NS_E_INVALID, "ns_backward needs checkpoint_every > 0, NS_FP64 and a fixed dt");
+  if (!I.rec_valid || I.rec_steps < 1)
+    return fail(s, NS_E_STATE, "no recorded steps since the velocity was last set");
+  DevGuard dg(s->device);
+  const Geo& g = I.g;
+  const int N = I.rec_steps, k = I.prm.checkpoint_every;
+  const size_t pb = I.pbytes;
+  // lazily allocate the adjoint work space
+  if (!I.R.u) HCK(s, alloc_state(I.R, I));
+  for (int c = 0; c < 3; c++) {
+    if (!I.lam[c]) HCK(s, dmalloc((void**)&I.lam[c], pb));
+    if (!I.z[c]) HCK(s, dmalloc((void**)&I.z[c], pb));
+  }
+  for (int b = 0; b < 2; b++)
+    if (!I.q[b]) HCK(s, dmalloc((void**)&I.q[b], pb));
+  while ((int)I.hist.size() < 3 * k) {
+    double* h = nullptr;
+    HCK(s, dmalloc((void**)&h, pb));
+    I.hist.push_back(h);
+  }
+  const bool timing = s->timing;
+  s->timing = false;
+  const int saved_pred = I.pred;
+  for (int c = 0; c < 3; c++) {
+    ns_status e = copy_in(s, I, I.lam[c], false, g_final[c], on_device);
+    if (e != NS_OK) { s->timing = timing; return e; }
+    HCK(s, launch_mask_unknowns(s->stream, g, I.lam[c], c));
+  }
+  ns_status ret = NS_OK;
+  I.qcur = 0;
+  HCK(s, hipMemsetAsync(I.q[0], 0, pb, s->stream));
+  const int nseg = (N + k - 1) / k;
+  for (int seg = nseg - 1; seg >= 0 && ret == NS_OK; seg--) {
+    const int s0 = seg * k, s1 = std::min(N, s0 + k);
+    // recompute the segment from its checkpoint, keeping u^n (boundary-filled)
+    ret = save_state(s, I, I.ck[seg], I.R);
+    for (int n = s0; n < s1 && ret == NS_OK; n++) {
+      double* hu = I.hist[3 * (n - s0)];
+      double* hv = I.hist[3 * (n - s0) + 1];
+      double* hw = I.hist[3 * (n - s0) + 2];
+      HCK(s, launch_bc_vel<double>(s->stream, g, (double*)I.R.u, (double*)I.R.v, (double*)I.R.w, I.prm.wall_vel));
+      HCK(s, hipMemcpyAsync(hu, I.R.u, pb, hipMemcpyDeviceToDevice, s->stream));
+      HCK(s, hipMemcpyAsync(hv, I.R.v, pb, hipMemcpyDeviceToDevice, s->stream));
+      HCK(s, hipMemcpyAsync(hw, I.R.w, pb, hipMemcpyDeviceToDevice, s->stream));
+      if (n + 1 < s1) ret = step_inst<double>(s, inst, I.R, false);
+    }
+    // reverse sweep over the segment
+    for (int n = s1 - 1; n >= s0 && ret == NS_OK; n--) {
+      // mu = P lambda: rhs = D lambda, A q = rhs, mu = lambda - G q (dt = 1)
+      for (int c = 0; c < 3; c++) {
+        HCK(s, launch_mask_unknowns(s->stream, g, I.lam[c], c));
+        for (int a = 0; a < 3; a++)
+          if (g.per[a]) HCK(s, launch_periodic<double>(s->stream, g, I.lam[c], a));
+      }
+      HCK(s, launch_rhs<double>(s->stream, g, I.lam[0], I.lam[1], I.lam[2], (double*)I.rhs, I.ctl, I.part,
+                                I.prm.tol, 1.0));
+      int sw = 0;
+      ret = solve_fp64(s, inst, I.q, &I.qcur, &sw);
+      if (ret != NS_OK) break;
+      if (s->hctl[inst].nonfinite) { ret = fail(s, NS_E_NONFINITE, "non-finite adjoint residual"); break; }
+      HCK(s, launch_p_ghosts<double>(s->stream, g, I.q[I.qcur]));
+      HCK(s, launch_project<double>(s->stream, g, I.lam[0], I.lam[1], I.lam[2], I.q[I.qcur], I.lam[0], I.lam[1],
+                                    I.lam[2], I.ctl, 1.0));
+      for (int c = 0; c < 3; c++) HCK(s, launch_mask_unknowns(s->stream, g, I.lam[c], c));
+      // lambda^n = B^T J(u^n)^T mu
+      const double* hu = I.hist[3 * (n - s0)];
+      const double* hv = I.hist[3 * (n - s0) + 1];
+      const double* hw = I.hist[3 * (n - s0) + 2];
+      HCK(s, launch_adj_fgh(s->stream, g, hu, hv, hw, I.lam[0], I.lam[1], I.lam[2], I.z[0], I.z[1], I.z[2],
+                            I.prm.dt, I.prm.re, I.prm.gamma));
+      HCK(s, launch_adj_fold(s->stream, g, I.z[0], I.z[1], I.z[2]));
+      for (int c = 0; c < 3; c++) std::swap(I.lam[c], I.z[c]);
+    }
+  }
+  I.pred = saved_pred;
+  s->timing = timing;
+  if (ret != NS_OK) return ret;
+  for (int c = 0; c < 3; c++) {
+    ns_status e = copy_out(s, I, I.lam[c], false, g_init[c], on_device);
+    if (e != NS_OK) return e;
+  }
+  return NS_OK;
+}
+
+void ns_destroy(ns_solver* s) {
+  if (!s) return;
+  DevGuard dg(s->device);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& I : s->in) free_inst(I);
+  for (auto e : s->pool) (void)hipEventDestroy(e);
+  if (s->hctl) (void)hipHostFree(s->hctl);
+  hipFree(s->stage);
+  delete s;
+}
+
+const char* ns_last_error(const ns_solver* s) {
+  return s ? s->err.c_str() : g_create_err.c_str();
+}
+
+}  // extern "C"

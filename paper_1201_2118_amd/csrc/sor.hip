@@ -1,0 +1,222 @@
+// sor.hip -- red-black SOR sweeps and the mixed-precision defect step.
+//
+// Operator: boundary-eliminated homogeneous-Neumann 7-point Laplacian,
+// A p = sum_nb a_nb (p_nb - p), a_nb = 1/h^2 for a neighbour inside the
+// domain (or its periodic image) and 0 across a wall.  Colour of a cell is
+// (i + j + k) mod 2 on 1-based interior indices; red (even) goes first.
+// A sweep maps p_in -> p_out out of place (so that a sweep never reads a
+// value another workgroup of the same sweep has already replaced):
+//   red:   p_out = p_in + omega r / a_c,   r = A p_in - rhs at the cell
+//   black: p_out = p_in + omega r' / a_c,  r' from the new red neighbours
+// which is (1 - omega) p + omega (sum a_nb p_nb - rhs) / a_c written as an
+// increment.  The residual r of p_in at every cell is summed in FP64 in the
+// same pass, so sweep m reports the RMS residual of iterate m - 1; the last
+// workgroup of the red pass applies the stop rule and raises ctl->done.
+#include <hip/hip_runtime.h>
+
+#include "ns_internal.h"
+#include "reduce.h"
+
+namespace ns {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(long n, int cap = 8192) {
+  long b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  return (int)(b < cap ? b : cap);
+}
+
+// Neighbour offsets and coefficients of cell (i, j, k): a missing neighbour
+// (wall) gets coefficient 0 and points at the cell itself so that the load
+// stays in bounds and finite.
+struct Nb {
+  long o[6];
+  double a[6];
+  double ac;
+};
+
+__device__ __forceinline__ Nb neighbours(const Geo& g, int i, int j, int k) {
+  Nb n;
+  const int sz[3] = {g.nx, g.ny, g.nz};
+  const int id[3] = {i, j, k};
+  const long st[3] = {1, g.sx, g.sxy};
+  const double h2[3] = {g.idx2, g.idy2, g.idz2};
+  n.ac = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    // minus side
+    if (id[d] > 1) { n.o[2 * d] = -st[d]; n.a[2 * d] = h2[d]; }
+    else if (g.per[d]) { n.o[2 * d] = (long)(sz[d] - 1) * st[d]; n.a[2 * d] = h2[d]; }
+    else { n.o[2 * d] = 0; n.a[2 * d] = 0.0; }
+    // plus side
+    if (id[d] < sz[d]) { n.o[2 * d + 1] = st[d]; n.a[2 * d + 1] = h2[d]; }
+    else if (g.per[d]) { n.o[2 * d + 1] = -(long)(sz[d] - 1) * st[d]; n.a[2 * d + 1] = h2[d]; }
+    else { n.o[2 * d + 1] = 0; n.a[2 * d + 1] = 0.0; }
+    n.ac += n.a[2 * d] + n.a[2 * d + 1];
+  }
+  return n;
+}
+
+struct Cell {
+  int i, j, k;
+  long c;
+};
+__device__ __forceinline__ Cell cell_of(const Geo& g, long t) {
+  Cell r;
+  long row = t / g.nx;
+  r.i = (int)(t - row * g.nx) + 1;
+  r.k = (int)(row / g.ny) + 1;
+  r.j = (int)(row - (long)(r.k - 1) * g.ny) + 1;
+  r.c = (long)r.k * g.sxy + (long)r.j * g.sx + r.i;
+  return r;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_sor_red(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restrict__ rhs, Geo g,
+          Ctl* ctl, double* part, double omega, int m, int itermax, int write, int zero_in,
+          int inner) {
+  __shared__ double sh[16];
+  __shared__ int sh_last;
+  if (ctl->done) return;
+  const long n = (long)g.nx * g.ny * g.nz;
+  double acc = 0.0;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const Cell cl = cell_of(g, t);
+    const Nb nb = neighbours(g, cl.i, cl.j, cl.k);
+    double r;
+    double pc = 0.0;
+    if (zero_in) {
+      r = -(double)rhs[cl.c];
+    } else {
+      pc = p_in[cl.c];
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 6; q++) s += nb.a[q] * ((double)p_in[cl.c + nb.o[q]] - pc);
+      r = s - (double)rhs[cl.c];
+    }
+    acc += r * r;
+    if (write && !((cl.i + cl.j + cl.k) & 1)) p_out[cl.c] = T(pc + omega * r / nb.ac);
+  }
+  double s = block_sum(acc, sh);
+  if (publish_partial(part, blockIdx.x, s, ctl, gridDim.x, &sh_last)) {
+    double tot = sum_partials(part, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      const double res = sqrt(tot / (double)n);
+      const int mm = m - 1;  // iterate whose residual this is
+      const double thr = inner ? ctl->thr_in : ctl->thr;
+      if (mm >= 1 || itermax == 0) {
+        if (inner) ctl->res_in = res; else ctl->res = res;
+        const bool fin = isfinite(res);
+        if (!(res > thr) || mm >= itermax || !fin) {
+          ctl->done = 1;
+          ctl->final_ = mm;
+          if (!fin) ctl->nonfinite = 1;
+        }
+      }
+      ctl->ticket = 0;
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_sor_black(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restrict__ rhs, Geo g,
+            const Ctl* ctl, double omega, int zero_in) {
+  if (ctl->done) return;
+  const long n = (long)g.nx * g.ny * g.nz;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const Cell cl = cell_of(g, t);
+    if (!((cl.i + cl.j + cl.k) & 1)) continue;
+    const Nb nb = neighbours(g, cl.i, cl.j, cl.k);
+    const double pc = zero_in ? 0.0 : (double)p_in[cl.c];
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; q++) s += nb.a[q] * ((double)p_out[cl.c + nb.o[q]] - pc);
+    const double r = s - (double)rhs[cl.c];
+    p_out[cl.c] = T(pc + omega * r / nb.ac);
+  }
+}
+
+// Mixed-precision outer step: p_out = p_in + e, r = rhs - A p_out (FP64
+// arithmetic, stored as FP32), RMS of the FP64 r into ctl->res; decides
+// outer convergence and sets the inner threshold eta * RMS(r).
+__global__ void __launch_bounds__(kBlock)
+k_defect(const double* __restrict__ p_in, const float* __restrict__ e, double* __restrict__ p_out,
+         const float* __restrict__ rhs, float* __restrict__ r, Geo g, Ctl* ctl, double* part,
+         double eta) {
+  __shared__ double sh[16];
+  __shared__ int sh_last;
+  const long n = (long)g.nx * g.ny * g.nz;
+  double acc = 0.0;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const Cell cl = cell_of(g, t);
+    const Nb nb = neighbours(g, cl.i, cl.j, cl.k);
+    const long c = cl.c;
+    const double pc = p_in[c] + (e ? (double)e[c] : 0.0);
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; q++) {
+      const long o = c + nb.o[q];
+      s += nb.a[q] * (p_in[o] + (e ? (double)e[o] : 0.0) - pc);
+    }
+    const double rr = (double)rhs[c] - s;
+    r[c] = (float)rr;
+    acc += rr * rr;
+    if (e) p_out[c] = pc;
+  }
+  double s = block_sum(acc, sh);
+  if (publish_partial(part, blockIdx.x, s, ctl, gridDim.x, &sh_last)) {
+    double tot = sum_partials(part, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      // an identically zero rhs needs no correction at all
+      const double res = ctl->rhs_rms == 0.0 ? 0.0 : sqrt(tot / (double)n);
+      const bool fin = isfinite(res);
+      ctl->res = res;
+      ctl->outer_done = !(res > ctl->thr) || !fin;
+      if (!fin) ctl->nonfinite = 1;
+      ctl->thr_in = eta * res;
+      ctl->done = ctl->outer_done;
+      ctl->final_ = 0;
+      ctl->ticket = 0;
+    }
+  }
+}
+
+}  // namespace
+
+int sor_num_blocks(const Geo& g, const SorShape&) {
+  return grid_for((long)g.nx * g.ny * g.nz);
+}
+
+template <class T>
+hipError_t launch_sor_sweep(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs,
+                            Ctl* ctl, double* part, double omega, int sweep_idx, int itermax,
+                            int write, int zero_in, int thr_is_inner, const SorShape&) {
+  const long n = (long)g.nx * g.ny * g.nz;
+  const int nb = grid_for(n);
+  k_sor_red<T><<<nb, kBlock, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, sweep_idx, itermax, write,
+                                      zero_in, thr_is_inner);
+  if (write) k_sor_black<T><<<nb, kBlock, 0, st>>>(p_in, p_out, rhs, g, ctl, omega, zero_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_defect(hipStream_t st, const Geo& g, const double* p_in, const float* e,
+                         double* p_out, const float* rhs, float* r, Ctl* ctl, double* part,
+                         double eta) {
+  const long n = (long)g.nx * g.ny * g.nz;
+  k_defect<<<grid_for(n), kBlock, 0, st>>>(p_in, e, p_out, rhs, r, g, ctl, part, eta);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sor_sweep<double>(hipStream_t, const Geo&, const double*, double*,
+                                             const double*, Ctl*, double*, double, int, int, int,
+                                             int, int, const SorShape&);
+template hipError_t launch_sor_sweep<float>(hipStream_t, const Geo&, const float*, float*,
+                                            const float*, Ctl*, double*, double, int, int, int, int,
+                                            int, const SorShape&);
+
+}  // namespace ns

@@ -1,0 +1,218 @@
+"""GPU parity of the HIP step against the FP64 oracle, through the C ABI.
+
+FP64 bar: 1e-12 relative (max-norm over the unknowns, pressure after mean
+removal) with equal sweep counts; the GPU contracts multiply-adds and sums
+residuals in another order, and both effects stay far below it because SOR
+is contractive.  Mixed precision: the stated 1e-5 relative velocity error.
+"""
+import numpy as np
+import pytest
+
+import nsworkloads as W
+import oracle
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _fixed_sweeps(prm, k):
+    return dict(prm, tol=0.0, itermax=k)
+
+
+# ---- single stages, via parameters that isolate them ----------------------
+
+@pytest.mark.parametrize("dims,bc", [((24, 20, 18), (0, 0, 0)), ((17, 13, 11), (0, 0, 0)),
+                                     ((16, 12, 8), (1, 1, 1)), ((12, 9, 10), (1, 0, 0)),
+                                     ((2, 2, 2), (0, 0, 0)), ((70, 3, 5), (0, 0, 0))])
+def test_predictor_rhs_and_projection(dims, bc):
+    """itermax = 0: boundary fill, predictor, rhs, (no sweep), projection."""
+    prm = W.cavity(dims[0], ny=dims[1], nz=dims[2], re=37.0, gamma=0.37)
+    prm.update(bc=bc, lx=1.1, ly=0.9, lz=1.3, itermax=0, dt=0.002)
+    prm["wall_vel"][2] = [0.2, 0.0, -0.3]
+    prm["g"] = (0.1, -0.2, 0.3)
+    init = U.random_state(prm, 1, amp=0.5)
+    s = U.gpu_run(prm, 1, init)
+    o, _ = U.oracle_run(prm, 1, init)
+    m = U.masks(prm)
+    for c, name in enumerate(("F", "G", "H")):
+        assert U.rel(s.get_np(name), o.work[c], m[c]) < 1e-13, name
+    assert U.rel(s.get_np("rhs"), o.rhs, m[3]) < 1e-12
+    assert np.array_equal(s.get_np("p")[m[3]], init["p"][m[3]])
+    U.compare_state(s, o, prm, 1e-13)
+
+
+@pytest.mark.parametrize("k", [1, 2, 7])
+@pytest.mark.parametrize("dims,bc", [((20, 16, 12), (0, 0, 0)), ((13, 11, 9), (0, 0, 0)),
+                                     ((16, 16, 6), (1, 1, 1)), ((10, 12, 7), (0, 1, 0))])
+def test_fixed_sweep_count(dims, bc, k):
+    """tol = 0: exactly k red-black sweeps, so the Poisson stage is compared
+    without any stop-rule decision."""
+    prm = W.cavity(dims[0], ny=dims[1], nz=dims[2], re=50.0, dt=0.003)
+    prm.update(_fixed_sweeps(prm, k), bc=bc)
+    init = U.random_state(prm, 2, amp=0.3)
+    s = U.gpu_run(prm, 1, init)
+    o, _ = U.oracle_run(prm, 1, init)
+    assert s.stats()["sweeps_total"] == k == o.stats.sweeps_total
+    U.compare_state(s, o, prm, 1e-12)
+    assert abs(s.stats()["res_last"] - o.stats.res_last) <= 1e-12 * o.stats.res_last
+
+
+# ---- whole steps ----------------------------------------------------------------
+
+def test_cavity_16_ten_steps():
+    """The 16^3 lid-driven cavity, Re 100, dt 0.01, gamma 0.5, omega 1.7,
+    tol 1e-6, 200 sweeps, 10 steps."""
+    prm, n = W.cavity_small()
+    s = U.gpu_run(prm, n)
+    o, rc = U.oracle_run(prm, n)
+    assert rc == 0
+    st = s.stats()
+    assert st["steps"] == 10 and st["steps_unconverged"] == 0
+    assert st["sweeps_total"] == o.stats.sweeps_total
+    assert st["sweeps_max"] == o.stats.sweeps_max
+    U.compare_state(s, o, prm, 1e-12)
+    assert abs(st["t"] - o.stats.t) < 1e-15
+
+
+@pytest.mark.parametrize("dims", [(17, 15, 13), (32, 8, 16), (9, 30, 5)])
+def test_cavity_ragged_sizes(dims):
+    prm = W.cavity(dims[0], ny=dims[1], nz=dims[2], dt=0.005)
+    s = U.gpu_run(prm, 4)
+    o, _ = U.oracle_run(prm, 4)
+    assert s.stats()["sweeps_total"] == o.stats.sweeps_total
+    U.compare_state(s, o, prm, 1e-12)
+
+
+def test_periodic_taylor_green():
+    prm = W.periodic_box(32, nz=4, dt=5e-4, gamma=0.0)
+    u, v, w, p = W.taylor_green(prm, amp=1.0, pert=1e-3, seed=2)
+    init = {"u": u, "v": v, "w": w, "p": p}
+    s = U.gpu_run(prm, 5, init)
+    o, _ = U.oracle_run(prm, 5, init)
+    assert s.stats()["sweeps_total"] == o.stats.sweeps_total
+    U.compare_state(s, o, prm, 1e-12)
+
+
+def test_cavity_128_parity():
+    """The 128^3 cavity (dt 5e-4), three steps: the sweep cap binds."""
+    prm, _ = W.cavity_128()
+    s = U.gpu_run(prm, 3)
+    o, _ = U.oracle_run(prm, 3)
+    assert s.stats()["sweeps_total"] == o.stats.sweeps_total == 600
+    U.compare_state(s, o, prm, 1e-12)
+
+
+def test_body_force_fields_and_adaptive_dt():
+    prm = W.cavity(12, ny=10, nz=14, re=80.0, dt=0.0, tau=0.5)
+    fx, fy, fz = W.gaussian_velocity(prm, 0.3, 9)
+    init = U.random_state(prm, 3, amp=0.2)
+    s = U.gpu_run(prm, 3, init, force=(fx, fy, fz))
+    o, _ = U.oracle_run(prm, 3, init, force=(fx, fy, fz))
+    assert abs(s.stats()["dt_last"] - o.stats.dt_last) <= 1e-15 * o.stats.dt_last
+    assert s.stats()["sweeps_total"] == o.stats.sweeps_total
+    U.compare_state(s, o, prm, 1e-12)
+
+
+def test_restart_and_determinism_are_bitwise():
+    prm = W.cavity(14, ny=12, nz=10)
+    a = U.gpu_run(prm, 6)
+    b = U.gpu_run(prm, 3)
+    c = U.gpu_run(prm, 0, {f: b.get_np(f) for f in "uvwp"})
+    c.step(3)
+    d = U.gpu_run(prm, 6)
+    for f in "uvwp":
+        assert np.array_equal(a.get_np(f), c.get_np(f)), f
+        assert np.array_equal(a.get_np(f), d.get_np(f)), f
+
+
+def test_several_instances_match_standalone_runs():
+    prms = [W.cavity(10, ny=12, nz=8), W.cavity(16, re=300.0, dt=0.004), W.periodic_box(8, nz=6, dt=1e-3)]
+    from paper_1201_2118_amd.solver import Solver
+    s = Solver(prms)
+    s.step(3)
+    for i, prm in enumerate(prms):
+        one = U.gpu_run(prm, 3)
+        for f in "uvwp":
+            assert np.array_equal(s.get_np(f, i), one.get_np(f)), (i, f)
+
+
+def test_nonfinite_state_is_reported():
+    from paper_1201_2118_amd import abi
+    prm = W.cavity(10)
+    init = U.random_state(prm, 4)
+    init["u"][5, 5, 5] = np.nan
+    s = U.gpu_run(prm, 0, init)
+    assert s.step(2, check=False) == abi.NS_E_NONFINITE
+    assert "non-finite" in s.last_error()
+
+
+# ---- mixed precision ---------------------------------------------------------------
+
+def test_mixed_matches_its_fp64_algorithm_and_fp64_oracle():
+    """FP32 storage and sweeps inside FP64 defect correction: against the
+    oracle running the same defect-correction algorithm in FP64 and against
+    the plain FP64 oracle, relative velocity error <= 1e-5."""
+    prm, n = W.cavity_small()
+    mp = dict(prm, precision="mixed")
+    s = U.gpu_run(mp, n)
+    od, _ = U.oracle_run(prm, n, mode=1)
+    o, _ = U.oracle_run(prm, n, mode=0)
+    m = U.masks(prm)
+    sd = U.velocity_scale([od.field(f) for f in "uvw"], prm)
+    so = U.velocity_scale([o.field(f) for f in "uvw"], prm)
+    for c, f in enumerate("uvw"):
+        assert U.vel_rel(s.get_np(f), od.field(f), m[c], sd) < 1e-5, f
+        assert U.vel_rel(s.get_np(f), o.field(f), m[c], so) < 1e-5, f
+    assert s.stats()["steps_unconverged"] == 0
+
+
+def test_mixed_fixed_budget_128():
+    prm, _ = W.cavity_128()
+    mp = dict(prm, precision="mixed")
+    s = U.gpu_run(mp, 2)
+    o, _ = U.oracle_run(prm, 2)
+    m = U.masks(prm)
+    sc = U.velocity_scale([o.field(f) for f in "uvw"], prm)
+    for c, f in enumerate("uvw"):
+        assert U.vel_rel(s.get_np(f), o.field(f), m[c], sc) < 1e-5, f
+    assert s.stats()["sweeps_total"] == 400
+
+
+# ---- adjoint ------------------------------------------------------------------------
+
+def _adjoint_case(n=10, steps=4, k=2, bc=(0, 0, 0)):
+    prm = W.cavity(n, ny=n - 2, nz=n + 1, re=400.0, dt=0.005, tol=1e-13, itermax=20000)
+    if bc[0]:
+        prm = W.periodic_box(n, ny=n - 2, nz=4, re=400.0, dt=0.005, gamma=0.5, tol=1e-13, itermax=20000)
+    prm["checkpoint_every"] = k
+    mk = [oracle.unknown_mask(prm, c) for c in range(3)]
+    u0 = [np.where(mk[c], f, 0.0) for c, f in enumerate(W.gaussian_velocity(prm, 1e-2, 5))]
+    tgt = [np.where(mk[c], f, 0.0) for c, f in enumerate(W.gaussian_velocity(prm, 1e-2, 6))]
+    return prm, u0, tgt, mk, steps
+
+
+@pytest.mark.parametrize("bc,k", [((0, 0, 0), 2), ((0, 0, 0), 3), ((1, 1, 1), 4)])
+def test_backward_matches_oracle_gradient(bc, k):
+    prm, u0, tgt, mk, steps = _adjoint_case(bc=bc, k=k, steps=5)
+    loss, grad, final = oracle.gradient(prm, *u0, tgt, steps)
+    s = U.gpu_run(prm, steps, {"u": u0[0], "v": u0[1], "w": u0[2]})
+    sc = U.velocity_scale(final, prm)
+    for c, f in enumerate("uvw"):
+        assert U.vel_rel(s.get_np(f), final[c], mk[c], sc) < 1e-12
+    gf = [np.where(mk[c], s.get_np(f) - tgt[c], 0.0) for c, f in enumerate("uvw")]
+    gi = [g.cpu().numpy() for g in s.backward(gf)]
+    for c in range(3):
+        assert U.rel(gi[c], grad[c], mk[c]) < 1e-10, c
+        assert not np.any(gi[c][~mk[c]])
+    # the forward state is untouched by the backward pass
+    for c, f in enumerate("uvw"):
+        assert U.vel_rel(s.get_np(f), final[c], mk[c], sc) < 1e-12
+
+
+def test_backward_needs_a_recording():
+    from paper_1201_2118_amd import abi
+    prm, u0, tgt, mk, steps = _adjoint_case()
+    s = U.gpu_run(prm, 0, {"u": u0[0], "v": u0[1], "w": u0[2]})
+    with pytest.raises(abi.NSError) as e:
+        s.backward(tgt)
+    assert e.value.code == abi.NS_E_STATE
