@@ -53,6 +53,7 @@ def measure(prm, steps, warmup):
     b = time.perf_counter()
     t1 = s.timing()
     st = s.stats()
+    tile = [t1.sor_tile[0], t1.sor_tile[1]]
     s.close()
     n = prm["nx"] * prm["ny"] * prm["nz"]
     secs = b - a
@@ -72,6 +73,7 @@ def measure(prm, steps, warmup):
         "sor_bytes_per_launch": sor_bytes / max(sor_launches, 1),
         "stage_ms": stage_ms,
         "stats": st,
+        "tile": tile,
     }
 
 
@@ -96,19 +98,20 @@ def cpu_baseline(prm):
     a = time.perf_counter()
     o.run(1)
     t_step2 = time.perf_counter() - a
+    extra = 40
     a = time.perf_counter()
-    for _ in range(2):
+    for _ in range(extra):
         o.sor_sweep(o.p, o.rhs)
         o.residual(o.p, o.rhs)
-    t_sweep = (time.perf_counter() - a) / 2
+    t_sweep = (time.perf_counter() - a) / extra
     sweeps = prm["itermax"]
     t_full = t_step2 + (sweeps - 2) * t_sweep
     n = prm["nx"] * prm["ny"] * prm["nz"]
     del o
     return {"value": n / t_full / 1e6, "unit": "Mcell-steps/s", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"one {prm['nx']}^3 step with 2 sweeps ({t_step2:.1f} s) plus 2 sweep+residual "
-                      f"passes ({t_sweep:.2f} s each), scaled to {sweeps} sweeps per step; FP64"}
+            "sample": f"one {prm['nx']}^3 step with 2 sweeps ({t_step2:.1f} s) plus {extra} sweep+residual "
+                      f"passes ({t_sweep:.3f} s each), scaled to {sweeps} sweeps per step; FP64"}
 
 
 def main():
@@ -147,7 +150,8 @@ def main():
     roof = {"bound": "hbm", "achieved": round(dom["sor_gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(dom["sor_gbs"] / PEAK_HBM_GBS, 4), "traffic": None,
             "kernel": "red-black SOR sweep (%s)" % ("FP32" if head is res.get("mixed") else "FP64"),
-            "bytes_per_launch": dom["sor_bytes_per_launch"], "avg_launch_ms": round(dom["sor_avg_ms"], 5)}
+            "bytes_per_launch": dom["sor_bytes_per_launch"], "avg_launch_ms": round(dom["sor_avg_ms"], 5),
+            "tile": dom["tile"]}
     out = {
         "metric": METRIC,
         "value": round(head["mcells"], 2),
@@ -173,7 +177,7 @@ def main():
         f = res["fp64"]
         out["fp64"] = {"value": round(f["mcells"], 2), "ms_per_step": round(f["ms_per_step"], 3),
                        "hbm_gbs_algorithmic": round(f["alg_gbs"], 1), "sor_gbs": round(f["sor_gbs"], 1),
-                       "sor_avg_ms": round(f["sor_avg_ms"], 5),
+                       "sor_avg_ms": round(f["sor_avg_ms"], 5), "tile": f["tile"],
                        "stage_ms": {k: round(v, 4) for k, v in f["stage_ms"].items()}}
     if not args.no_cpu:
         log("cpu baseline (oracle)")

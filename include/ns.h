@@ -97,6 +97,10 @@ typedef struct {
   int32_t precision;      /* NS_FP64 or NS_MIXED */
   int32_t checkpoint_every; /* > 0: record checkpoints every k steps for ns_backward */
   int32_t flags;          /* NS_ALLOW_UNSTABLE | NS_TIMING */
+  int32_t tile[2];        /* fused SOR sweep shape: {rows per workgroup (4, 8 or 12),
+                             z planes per chunk (0 = whole column)}; {0, 0} = chosen by the
+                             autotuner; rows = -1 selects the unfused one-pass-per-colour
+                             sweeps (reference path). Results do not depend on it. */
 } ns_params;
 
 typedef struct {
@@ -119,6 +123,7 @@ typedef struct {
   double ms[NS_T_COUNT];
   int64_t launches[NS_T_COUNT];
   int64_t sor_bytes;     /* algorithmic HBM bytes of the SOR launches timed */
+  int32_t sor_tile[2];   /* sweep shape in use on instance 0 (see ns_params.tile) */
 } ns_timing;
 
 /* Fill *p with the defaults of the 16^3 lid-driven cavity (Re 100, dt 0.01,

@@ -40,6 +40,7 @@ class ns_params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("checkpoint_every", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("tile", ctypes.c_int32 * 2),
     ]
 
 
@@ -57,7 +58,7 @@ class ns_stats(ctypes.Structure):
 
 class ns_timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * NS_T_COUNT), ("launches", ctypes.c_int64 * NS_T_COUNT),
-                ("sor_bytes", ctypes.c_int64)]
+                ("sor_bytes", ctypes.c_int64), ("sor_tile", ctypes.c_int32 * 2)]
 
 
 class NSError(RuntimeError):

@@ -427,10 +427,11 @@ hipError_t launch_fgh(hipStream_t st, const Geo& g, const T* u, const T* v, cons
 
 size_t reduce_blocks(const Geo& g) {
   long n = (long)g.nx * g.ny * g.nz;
-  size_t b = (size_t)grid_for(n);
-  size_t s = (size_t)sor_num_blocks(g, SorShape{8, 0});
-  size_t m = b > s ? b : s;
-  return 4 * m + 64 + 65536;
+  size_t m = (size_t)grid_for(n);
+  // the fused sweep has the most workgroups with 4 rows and 1-plane chunks
+  const size_t f = (size_t)fused_num_blocks(g, SorShape{4, 1});
+  if (f > m) m = f;
+  return 4 * m + 64;
 }
 
 template <class T>

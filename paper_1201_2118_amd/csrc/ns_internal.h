@@ -40,10 +40,13 @@ struct Ctl {
   int32_t pad_[3];
 };
 
-// Tunables of the fused red-black sweep (chosen per grid by the autotuner).
+// Tunables of the red-black sweep (chosen per grid by the autotuner).
+// ty > 0: fused single-pass kernel with ty interior rows per workgroup (the
+// x width is fixed at 60 = 64 - 4 halo) and zc planes per z chunk (0 =
+// whole column); ty < 0: unfused reference kernels (one pass per colour).
 struct SorShape {
-  int ty;   // interior rows per workgroup (x width is fixed at 60 = 64 - 4 halo)
-  int zc;   // planes per z chunk (0 = whole column)
+  int ty;
+  int zc;
 };
 
 // ---- kernel launchers (kernels.hip / sor.hip / adjoint.hip) ----
@@ -84,6 +87,16 @@ hipError_t launch_defect(hipStream_t st, const Geo& g, const double* p_in, const
 
 size_t reduce_blocks(const Geo& g);  // partial-sum slots any reduction may need
 int sor_num_blocks(const Geo& g, const SorShape& s);
+// Fused sweep (one pass): shape.ty rows per workgroup in {4, 8, 12},
+// shape.zc planes per z chunk (0 = whole column).
+template <class T> hipError_t launch_sor_fused(hipStream_t st, const Geo& g, const T* p_in, T* p_out,
+                                              const T* rhs, Ctl* ctl, double* part, double omega,
+                                              int sweep_idx, int itermax, int write, int zero_in,
+                                              int thr_is_inner, const SorShape& shape);
+int fused_num_blocks(const Geo& g, const SorShape& s);
+bool fused_shape_ok(const SorShape& s);
+int fused_resident(int ty, bool f32);       // workgroups resident on the device at once
+int fused_columns(const Geo& g, int ty);    // x-y tiles of one z chunk
 
 // Adjoint of the predictor in gather form (FP64 only): z = B^T J_Phi(u)^T mu.
 hipError_t launch_adj_fgh(hipStream_t st, const Geo& g, const double* u, const double* v,

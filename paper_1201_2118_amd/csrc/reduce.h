@@ -7,12 +7,19 @@
 
 namespace ns {
 
-// Sum over a 1D workgroup (blockDim.x a multiple of 64, at most 1024) in a
-// fixed order: wave64 shuffles, then the per-wave sums by wave 0.  The
-// result is valid in thread 0.
+// Flattened thread index and workgroup size (1D, 2D or 3D workgroups).
+__device__ __forceinline__ int flat_tid() {
+  return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+}
+__device__ __forceinline__ int flat_size() { return blockDim.x * blockDim.y * blockDim.z; }
+
+// Sum over a workgroup (size a multiple of 64, at most 1024) in a fixed
+// order: wave64 shuffles, then the per-wave sums by wave 0.  The result is
+// valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh /* >= 16 */) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int t = flat_tid();
+  const int lane = t & 63, wid = t >> 6, nw = flat_size() >> 6;
   __syncthreads();
   if (lane == 0) sh[wid] = v;
   __syncthreads();
@@ -26,7 +33,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh /* >= 16 */) {
 
 __device__ __forceinline__ double block_max(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int t = flat_tid();
+  const int lane = t & 63, wid = t >> 6, nw = flat_size() >> 6;
   __syncthreads();
   if (lane == 0) sh[wid] = v;
   __syncthreads();
@@ -43,7 +51,7 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 // (fence-acquire done here) and must reset ctl->ticket.
 __device__ __forceinline__ bool publish_partial(double* part, int slot, double v, Ctl* ctl,
                                                 unsigned nblocks, int* sh_last) {
-  if (threadIdx.x == 0) {
+  if (flat_tid() == 0) {
     part[slot] = v;
     __threadfence();
     unsigned t = atomicAdd(&ctl->ticket, 1u);
@@ -59,13 +67,13 @@ __device__ __forceinline__ bool publish_partial(double* part, int slot, double v
 // then block_sum); valid in thread 0.
 __device__ __forceinline__ double sum_partials(const double* part, unsigned n, double* sh) {
   double s = 0.0;
-  for (unsigned i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  for (unsigned i = flat_tid(); i < n; i += flat_size()) s += part[i];
   return block_sum(s, sh);
 }
 
 __device__ __forceinline__ double max_partials(const double* part, unsigned n, double* sh) {
   double s = 0.0;
-  for (unsigned i = threadIdx.x; i < n; i += blockDim.x) s = fmax(s, part[i]);
+  for (unsigned i = flat_tid(); i < n; i += flat_size()) s = fmax(s, part[i]);
   return block_max(s, sh);
 }
 

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -182,6 +183,9 @@ ns_status validate(const ns_params& p, int idx) {
   for (int c = 0; c < 3; c++)
     if (!std::isfinite(p.g[c])) return bad("body force must be finite");
   if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING)) return bad("unknown flag bits");
+  if (!(p.tile[0] == -1 || p.tile[0] == 0 || p.tile[0] == 4 || p.tile[0] == 8 || p.tile[0] == 12))
+    return bad("tile[0] must be -1, 0, 4, 8 or 12");
+  if (p.tile[1] < 0) return bad("tile[1] must be >= 0");
   if (p.dt > 0 && !(p.flags & NS_ALLOW_UNSTABLE)) {
     const double dx = p.lx / p.nx, dy = p.ly / p.ny, dz = p.lz / p.nz;
     const double diff = p.dt / p.re * (1 / (dx * dx) + 1 / (dy * dy) + 1 / (dz * dz));
@@ -200,6 +204,103 @@ ns_status validate(const ns_params& p, int idx) {
   return NS_OK;
 }
 
+// Sweep shape: the caller's tile descriptor, or a size-based default that
+// the autotuner may replace (see autotune()).
+SorShape pick_shape(const ns_params& p, const Geo& g) {
+  if (p.tile[0] < 0) return SorShape{-1, 0};
+  if (p.tile[0] > 0) return SorShape{p.tile[0], p.tile[1]};
+  const long n = (long)g.nx * g.ny * g.nz;
+  if (n >= (1L << 24)) return SorShape{8, 128};
+  return SorShape{8, 0};
+}
+
+hipError_t dmalloc(void** p, size_t bytes);
+
+// ---- autotuner ---------------------------------------------------------------
+// For grids of at least 2^21 cells with tile = {0, 0}: time candidate shapes
+// on the instance's own (still zero) pressure buffers with HIP events, 1
+// warm-up and 3 timed sweeps each, and keep the fastest.  Candidates: rows
+// 4 / 8 / 12, each with the whole column, z chunks 32 / 64 / 128, and the z
+// chunks that make the tile count just fit k times the resident workgroups
+// (k = 1..8), which avoids a nearly empty last round of tiles.  Results are
+// cached per grid shape, storage precision and boundary kind for the life
+// of the process.
+struct TuneKey {
+  int nx, ny, nz, esz, per;
+  bool operator==(const TuneKey& o) const {
+    return nx == o.nx && ny == o.ny && nz == o.nz && esz == o.esz && per == o.per;
+  }
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, SorShape>> g_tune_cache;
+
+template <class T>
+ns_status tune_run(ns_solver* s, Inst& I, Ctl* tctl, const SorShape& sh, float* ms) {
+  hipEvent_t a, b;
+  HCK(s, hipEventCreate(&a));
+  HCK(s, hipEventCreate(&b));
+  const T* in = (const T*)(I.mixed ? (void*)I.e[0] : (void*)I.s.p[0]);
+  T* out = (T*)(I.mixed ? (void*)I.e[1] : (void*)I.s.p[1]);
+  const T* rhs = (const T*)(I.mixed ? (void*)I.r : I.rhs);
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < 4 && e == hipSuccess; it++) {
+    if (it == 1) e = hipEventRecord(a, s->stream);
+    // sweep index 1: the residual of iterate 0 is never a stop decision
+    if (e == hipSuccess) e = launch_sor_sweep<T>(s->stream, I.g, in, out, rhs, tctl, I.part, I.prm.omega, 1, 1 << 30,
+                                                1, 0, 0, sh);
+  }
+  if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail_hip(s, "autotune", e);
+  return NS_OK;
+}
+
+ns_status autotune(ns_solver* s, Inst& I) {
+  const long n = (long)I.g.nx * I.g.ny * I.g.nz;
+  if (I.prm.tile[0] != 0 || n < (1L << 21)) return NS_OK;
+  const TuneKey key{I.g.nx, I.g.ny, I.g.nz, (int)I.esz, I.g.per[0] | (I.g.per[1] << 1) | (I.g.per[2] << 2)};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& kv : g_tune_cache)
+      if (kv.first == key) { I.shape = kv.second; return NS_OK; }
+  }
+  Ctl* tctl = nullptr;
+  HCK(s, dmalloc((void**)&tctl, sizeof(Ctl)));
+  const int rows[3] = {4, 8, 12};
+  float best = 1e30f;
+  SorShape pick = I.shape;
+  ns_status st = NS_OK;
+  for (int r = 0; r < 3 && st == NS_OK; r++) {
+    std::vector<int> zcs = {0, 32, 64, 128};
+    const int res = fused_resident(rows[r], I.mixed);
+    const int cols = fused_columns(I.g, rows[r]);
+    for (int k = 1; k <= 8 && res > 0; k++) {
+      const int ntz = (int)((long)k * res / cols);
+      if (ntz < 1) continue;
+      const int zc = (I.g.nz + ntz - 1) / ntz;
+      if (zc >= 8 && zc < I.g.nz) zcs.push_back(zc);
+    }
+    std::sort(zcs.begin(), zcs.end());
+    zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
+    for (int zc : zcs) {
+      if (st != NS_OK) break;
+      const SorShape sh{rows[r], zc};
+      float ms = 0.f;
+      st = I.mixed ? tune_run<float>(s, I, tctl, sh, &ms) : tune_run<double>(s, I, tctl, sh, &ms);
+      if (st == NS_OK && ms < best) { best = ms; pick = sh; }
+    }
+  }
+  (void)hipFree(tctl);
+  if (st != NS_OK) return st;
+  I.shape = pick;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache.push_back({key, pick});
+  return NS_OK;
+}
+
 hipError_t dmalloc(void** p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) { *p = nullptr; return e; }
@@ -207,23 +308,23 @@ hipError_t dmalloc(void** p, size_t bytes) {
 }
 
 void free_state(State& s) {
-  hipFree(s.u); hipFree(s.v); hipFree(s.w);
-  hipFree(s.p[0]); hipFree(s.p[1]);
+  (void)hipFree(s.u); (void)hipFree(s.v); (void)hipFree(s.w);
+  (void)hipFree(s.p[0]); (void)hipFree(s.p[1]);
   s = State{};
 }
 
 void free_inst(Inst& I) {
   free_state(I.s);
-  hipFree(I.F); hipFree(I.G); hipFree(I.H); hipFree(I.rhs);
-  for (int c = 0; c < 3; c++) hipFree(I.frc[c]);
-  hipFree(I.e[0]); hipFree(I.e[1]); hipFree(I.r);
-  hipFree(I.part); hipFree(I.ctl);
+  (void)hipFree(I.F); (void)hipFree(I.G); (void)hipFree(I.H); (void)hipFree(I.rhs);
+  for (int c = 0; c < 3; c++) (void)hipFree(I.frc[c]);
+  (void)hipFree(I.e[0]); (void)hipFree(I.e[1]); (void)hipFree(I.r);
+  (void)hipFree(I.part); (void)hipFree(I.ctl);
   for (auto& c : I.ck) free_state(c);
   I.ck.clear();
   free_state(I.R);
-  for (int c = 0; c < 3; c++) { hipFree(I.lam[c]); hipFree(I.z[c]); }
-  hipFree(I.q[0]); hipFree(I.q[1]);
-  for (auto* h : I.hist) hipFree(h);
+  for (int c = 0; c < 3; c++) { (void)hipFree(I.lam[c]); (void)hipFree(I.z[c]); }
+  (void)hipFree(I.q[0]); (void)hipFree(I.q[1]);
+  for (auto* h : I.hist) (void)hipFree(h);
   I.hist.clear();
 }
 
@@ -570,6 +671,7 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
     if (hipMemcpy(I.ctl, &c, sizeof c, hipMemcpyHostToDevice) != hipSuccess)
       return bail(NS_E_DEVICE, "control block upload failed");
     I.rec_valid = I.prm.checkpoint_every > 0;
+    I.shape = pick_shape(I.prm, I.g);
   }
   // staging buffer for FP32 conversions of host data
   bool any_mixed = false;
@@ -587,6 +689,15 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
                                                    (double*)I.s.w, I.prm.wall_vel);
     if (e != hipSuccess) return bail(NS_E_DEVICE, std::string("boundary fill failed: ") + hipGetErrorString(e));
   }
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(NS_E_DEVICE, "stream synchronisation failed");
+  for (auto& I : s->in) {
+    if (autotune(s, I) != NS_OK) return bail(NS_E_DEVICE, "autotune: " + s->err);
+  }
+  // the trial sweeps wrote the second pressure buffer: clear it again
+  for (auto& I : s->in)
+    if (hipMemsetAsync(I.s.p[1], 0, I.pbytes, s->stream) != hipSuccess ||
+        (I.mixed && hipMemsetAsync(I.e[1], 0, (size_t)I.g.ntot * 4, s->stream) != hipSuccess))
+      return bail(NS_E_DEVICE, "buffer clear failed");
   if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(NS_E_DEVICE, "stream synchronisation failed");
   *out = s;
   return NS_OK;
@@ -690,6 +801,8 @@ ns_status ns_step(ns_solver* s, int32_t nsteps, ns_stats* stats) {
 ns_status ns_get_timing(const ns_solver* s, ns_timing* out) {
   if (!s || !out) return fail(const_cast<ns_solver*>(s), NS_E_INVALID, "NULL argument");
   *out = s->tm;
+  out->sor_tile[0] = s->in[0].shape.ty;
+  out->sor_tile[1] = s->in[0].shape.zc;
   return NS_OK;
 }
 
@@ -794,7 +907,7 @@ void ns_destroy(ns_solver* s) {
   for (auto& I : s->in) free_inst(I);
   for (auto e : s->pool) (void)hipEventDestroy(e);
   if (s->hctl) (void)hipHostFree(s->hctl);
-  hipFree(s->stage);
+  (void)hipFree(s->stage);
   delete s;
 }
 

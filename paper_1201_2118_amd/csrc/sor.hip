@@ -188,14 +188,19 @@ k_defect(const double* __restrict__ p_in, const float* __restrict__ e, double* _
 
 }  // namespace
 
-int sor_num_blocks(const Geo& g, const SorShape&) {
-  return grid_for((long)g.nx * g.ny * g.nz);
+int sor_num_blocks(const Geo& g, const SorShape& s) {
+  const int a = grid_for((long)g.nx * g.ny * g.nz);
+  const int b = s.ty > 0 ? fused_num_blocks(g, s) : 0;
+  return a > b ? a : b;
 }
 
 template <class T>
 hipError_t launch_sor_sweep(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs,
                             Ctl* ctl, double* part, double omega, int sweep_idx, int itermax,
-                            int write, int zero_in, int thr_is_inner, const SorShape&) {
+                            int write, int zero_in, int thr_is_inner, const SorShape& shape) {
+  if (shape.ty > 0)
+    return launch_sor_fused<T>(st, g, p_in, p_out, rhs, ctl, part, omega, sweep_idx, itermax, write, zero_in,
+                               thr_is_inner, shape);
   const long n = (long)g.nx * g.ny * g.nz;
   const int nb = grid_for(n);
   k_sor_red<T><<<nb, kBlock, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, sweep_idx, itermax, write,

@@ -1,0 +1,269 @@
+// sor_fused.hip -- one red-black SOR sweep in one pass over HBM.
+//
+// A workgroup owns a column of TX x TY interior cells (TX = 60) and marches
+// it through a chunk of z planes.  Its 64 x (TY + 4) threads cover the
+// column plus a 2-cell halo in x and y (one x row per wave64, so every load
+// is a contiguous 512-byte row in FP64).  Each thread keeps the planes of
+// its own (x, y) position in registers and exchanges x / y neighbours
+// through two double-buffered LDS planes, with one workgroup barrier per z
+// plane.  With plane L the newest loaded:
+//   - residual of the input iterate at plane L-1 (tile cells),
+//   - red update at plane L-1 (tile + 1-cell halo; needs input at L-2..L),
+//   - black update at plane L-2 (tile; needs the new red values at L-3..L-1),
+//   - the tile row of plane L-2 is written out.
+// The halo is recomputed redundantly, so no workgroup reads a value another
+// workgroup writes in the same sweep; input and output are different
+// buffers.  The arithmetic per cell is that of the unfused sweep: the
+// residual r = sum_nb a_nb (p_nb - p) - rhs and p + (omega / a_c) r.
+// Positions outside the domain load a clamped (wall) or wrapped (periodic)
+// cell, so every load is in bounds and finite; across a wall the
+// coefficient is zero.
+#include <hip/hip_runtime.h>
+
+#include "ns_internal.h"
+#include "reduce.h"
+
+namespace ns {
+
+namespace {
+
+constexpr int kW = 64;   // threads per row (x), one wave
+constexpr int kTX = 60;  // interior cells per row
+
+// Cell index that a virtual position loads: one periodic image on each
+// side, clamped beyond (positions that far out are never used).
+__device__ __forceinline__ int wrapc(int i, int n, int per) {
+  if (i < 1) return (per && i + n >= 1) ? i + n : 1;
+  if (i > n) return (per && i - n <= n) ? i - n : n;
+  return i;
+}
+
+// Barrier that orders LDS only: global loads issued before it stay in
+// flight (a full __syncthreads would wait for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Compute type: FP64 for FP64 storage; FP32 storage sweeps in FP32 (the
+// correction equation of the mixed form), with FP64 residual sums either way.
+template <class T> struct Acc { using type = double; };
+template <> struct Acc<float> { using type = float; };
+
+template <class T, int TYH>
+__global__ void __launch_bounds__(kW * TYH)
+k_sor_fused(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restrict__ rhs, Geo g,
+            Ctl* ctl, double* part, double omega, int m, int itermax, int write, int zero_in, int inner,
+            int zc, int ntx, int nty, int ntiles) {
+  using A = typename Acc<T>::type;
+  constexpr int TY = TYH - 4;
+  __shared__ T sp[2][TYH * kW];
+  __shared__ T sr[2][TYH * kW];
+  __shared__ double shred[16];
+  __shared__ int sh_last;
+  if (ctl->done) return;
+
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int lid = ty * kW + tx;
+  const int per0 = g.per[0], per1 = g.per[1], per2 = g.per[2];
+  const bool halo1 = tx >= 1 && tx <= kTX + 2 && ty >= 1 && ty <= TY + 2;
+  const A idz2 = (A)g.idz2;
+  double acc = 0.0;
+
+  // Persistent loop over tiles.  Workgroup b runs on XCD b % 8; the tiles
+  // are split into 8 contiguous ranges, one per XCD, dealt round-robin to
+  // that XCD's workgroups, so the tiles in flight on one XCD are neighbours.
+  const int G = gridDim.x;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int nwg_x = (G >> 3) + (xcd < (G & 7) ? 1 : 0);  // workgroups on this XCD
+  const int lo = (int)((long)ntiles * xcd / 8), hi = (int)((long)ntiles * (xcd + 1) / 8);
+  for (int tile = lo + slot; tile < hi; tile += nwg_x) {
+    const int bx = tile % ntx;
+    const int rest = tile / ntx;
+    const int by = rest % nty;
+    const int bz = rest / nty;
+    const int i = bx * kTX + tx - 1;  // virtual global x index (1-based interior)
+    const int j = by * TY + ty - 1;
+    const int z0 = 1 + bz * zc;
+    const int z1 = min(g.nz, z0 + zc - 1);
+    const long col = (long)wrapc(j, g.ny, per1) * g.sx + wrapc(i, g.nx, per0);
+    const bool own = tx >= 2 && tx <= kTX + 1 && ty >= 2 && ty <= TY + 1 && i <= g.nx && j <= g.ny;
+
+    // boundary-eliminated coefficients in x and y (fixed per thread)
+    const A axm = (i > 1 || per0) ? (A)g.idx2 : A(0);
+    const A axp = (i < g.nx || per0) ? (A)g.idx2 : A(0);
+    const A aym = (j > 1 || per1) ? (A)g.idy2 : A(0);
+    const A ayp = (j < g.ny || per1) ? (A)g.idy2 : A(0);
+    const double axy = ((double)axm + (double)axp) + ((double)aym + (double)ayp);
+    // omega / a_c for the first, interior and last plane
+    const double az_lo = per2 ? 2.0 * g.idz2 : g.idz2;
+    const A w_lo = (A)(omega / (axy + az_lo));
+    const A w_mid = (A)(omega / (axy + 2.0 * g.idz2));
+    const int cpar = (i + j) & 1;
+
+    auto plane = [&](int k) -> long { return (long)wrapc(k, g.nz, per2) * g.sxy + col; };
+    auto ldp = [&](int k) -> A { return zero_in ? A(0) : (A)p_in[plane(k)]; };
+    auto ldr = [&](int k) -> A { return halo1 ? (A)rhs[plane(k)] : A(0); };
+
+    A pm2 = ldp(z0 - 2), pm1 = ldp(z0 - 1), p0 = ldp(z0), pn1 = ldp(z0 + 1);
+    A rh1 = ldr(z0 - 1), rq0 = ldr(z0);  // rhs at L-1 and L
+    A rh2 = A(0);                        // rhs at L-2
+    A rnA = A(0), rnB = A(0);            // new red values at L-3, L-2
+
+    for (int L = z0; L <= z1 + 2; L++) {
+      // loads two planes ahead: input at L+2, rhs at L+1
+      const A pn2 = ldp(L + 2);
+      const A rq1 = ldr(L + 1);
+
+      sp[(L - 1) & 1][lid] = (T)pm1;
+      lds_barrier();
+
+      // residual of the input and red update at plane k1 = L - 1
+      const int k1 = L - 1;
+      const A azm1 = (k1 > 1 || per2) ? idz2 : A(0);
+      const A azp1 = (k1 < g.nz || per2) ? idz2 : A(0);
+      A rnew = pm1;
+      if (halo1) {
+        const T* P = sp[(L - 1) & 1];
+        const A pc = pm1;
+        const A s = axm * ((A)P[lid - 1] - pc) + axp * ((A)P[lid + 1] - pc) +
+                    aym * ((A)P[lid - kW] - pc) + ayp * ((A)P[lid + kW] - pc) +
+                    azm1 * (pm2 - pc) + azp1 * (p0 - pc);
+        const A r = s - rh1;
+        if (own && k1 >= z0 && k1 <= z1) acc += (double)r * (double)r;
+        if (!((cpar + k1) & 1)) {
+          const A wk = (k1 > 1 && k1 < g.nz) ? w_mid : w_lo;
+          rnew = (A)(T)(pc + wk * r);  // stored precision, as the LDS copy
+        }
+      }
+      sr[(L - 1) & 1][lid] = (T)rnew;
+
+      // black update and output at plane k2 = L - 2
+      const int k2 = L - 2;
+      if (own && k2 >= z0 && k2 <= z1) {
+        A out;
+        if ((cpar + k2) & 1) {
+          const T* R = sr[(L - 2) & 1];
+          const A pc = pm2;
+          const A azm2 = (k2 > 1 || per2) ? idz2 : A(0);
+          const A azp2 = (k2 < g.nz || per2) ? idz2 : A(0);
+          const A s = axm * ((A)R[lid - 1] - pc) + axp * ((A)R[lid + 1] - pc) +
+                      aym * ((A)R[lid - kW] - pc) + ayp * ((A)R[lid + kW] - pc) +
+                      azm2 * (rnA - pc) + azp2 * (rnew - pc);
+          const A r = s - rh2;
+          const A wk = (k2 > 1 && k2 < g.nz) ? w_mid : w_lo;
+          out = pc + wk * r;
+        } else {
+          out = rnB;
+        }
+        if (write) p_out[(long)k2 * g.sxy + col] = (T)out;
+      }
+      pm2 = pm1;
+      pm1 = p0;
+      p0 = pn1;
+      pn1 = pn2;
+      rnA = rnB;
+      rnB = rnew;
+      rh2 = rh1;
+      rh1 = rq0;
+      rq0 = rq1;
+    }
+    // the next tile reuses the LDS planes
+    __syncthreads();
+  }
+
+  // FP64 residual partial of this workgroup; the last one applies the stop rule
+  const long n = (long)g.nx * g.ny * g.nz;
+  double s = block_sum(acc, shred);
+  if (publish_partial(part, blockIdx.x, s, ctl, gridDim.x, &sh_last)) {
+    double tot = sum_partials(part, gridDim.x, shred);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+      const double res = sqrt(tot / (double)n);
+      const int mm = m - 1;
+      const double thr = inner ? ctl->thr_in : ctl->thr;
+      if (mm >= 1 || itermax == 0) {
+        if (inner) ctl->res_in = res; else ctl->res = res;
+        const bool fin = isfinite(res);
+        if (!(res > thr) || mm >= itermax || !fin) {
+          ctl->done = 1;
+          ctl->final_ = mm;
+          if (!fin) ctl->nonfinite = 1;
+        }
+      }
+      ctl->ticket = 0;
+    }
+  }
+}
+
+// Resident workgroups of one kernel on this device (occupancy x CUs),
+// cached per kernel.
+template <class T, int TYH>
+int resident_groups() {
+  static int cached = 0;
+  if (cached > 0) return cached;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sor_fused<T, TYH>, kW * TYH, 0) != hipSuccess)
+    return 0;
+  cached = cus * (per_cu > 0 ? per_cu : 1);
+  return cached;
+}
+
+template <class T, int TYH>
+hipError_t launch_ty(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl,
+                     double* part, double omega, int m, int itermax, int write, int zero_in, int inner,
+                     int zc) {
+  constexpr int TY = TYH - 4;
+  const int ntx = (g.nx + kTX - 1) / kTX;
+  const int nty = (g.ny + TY - 1) / TY;
+  const int ntz = (g.nz + zc - 1) / zc;
+  const int ntiles = ntx * nty * ntz;
+  int nb = resident_groups<T, TYH>();
+  if (nb <= 0 || nb > ntiles) nb = ntiles;
+  k_sor_fused<T, TYH><<<nb, dim3(kW, TYH), 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write,
+                                                    zero_in, inner, zc, ntx, nty, ntiles);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int fused_num_blocks(const Geo& g, const SorShape& s) {
+  const int ty = s.ty;
+  const int zc = s.zc > 0 ? s.zc : g.nz;
+  return ((g.nx + kTX - 1) / kTX) * ((g.ny + ty - 1) / ty) * ((g.nz + zc - 1) / zc);
+}
+
+bool fused_shape_ok(const SorShape& s) { return s.ty == 4 || s.ty == 8 || s.ty == 12; }
+
+int fused_resident(int ty, bool f32) {
+  switch (ty) {
+    case 4: return f32 ? resident_groups<float, 8>() : resident_groups<double, 8>();
+    case 8: return f32 ? resident_groups<float, 12>() : resident_groups<double, 12>();
+    case 12: return f32 ? resident_groups<float, 16>() : resident_groups<double, 16>();
+    default: return 0;
+  }
+}
+
+int fused_columns(const Geo& g, int ty) { return ((g.nx + kTX - 1) / kTX) * ((g.ny + ty - 1) / ty); }
+
+template <class T>
+hipError_t launch_sor_fused(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl,
+                            double* part, double omega, int m, int itermax, int write, int zero_in, int inner,
+                            const SorShape& s) {
+  const int zc = s.zc > 0 ? (s.zc < g.nz ? s.zc : g.nz) : g.nz;
+  switch (s.ty) {
+    case 4: return launch_ty<T, 8>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+    case 8: return launch_ty<T, 12>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+    case 12: return launch_ty<T, 16>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_sor_fused<double>(hipStream_t, const Geo&, const double*, double*, const double*, Ctl*,
+                                             double*, double, int, int, int, int, int, const SorShape&);
+template hipError_t launch_sor_fused<float>(hipStream_t, const Geo&, const float*, float*, const float*, Ctl*,
+                                            double*, double, int, int, int, int, int, const SorShape&);
+
+}  // namespace ns

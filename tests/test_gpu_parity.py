@@ -216,3 +216,50 @@ def test_backward_needs_a_recording():
     with pytest.raises(abi.NSError) as e:
         s.backward(tgt)
     assert e.value.code == abi.NS_E_STATE
+
+
+# ---- fused sweep shapes ------------------------------------------------------------
+
+@pytest.mark.parametrize("tile", [(4, 0), (8, 5), (12, 3), (8, 1), (4, 2)])
+@pytest.mark.parametrize("dims,bc", [((70, 20, 13), (0, 0, 0)), ((16, 12, 8), (1, 1, 1)),
+                                     ((61, 10, 7), (0, 1, 0)), ((3, 130, 4), (0, 0, 0)),
+                                     ((122, 7, 6), (1, 0, 1))])
+def test_fused_sweep_shapes_match_unfused_and_oracle(dims, bc, tile):
+    """Every workgroup shape and z chunking (ragged tiles in x, y and z)
+    gives the unfused sweeps' result and the oracle's, for fixed sweeps."""
+    prm = W.cavity(dims[0], ny=dims[1], nz=dims[2], re=50.0, dt=5e-4, tol=0.0, itermax=5)
+    prm["bc"] = bc
+    init = U.random_state(prm, 8, amp=0.3)
+    f = U.gpu_run(dict(prm, tile=tile), 1, init)
+    ref = U.gpu_run(dict(prm, tile=(-1, 0)), 1, init)
+    o, _ = U.oracle_run(prm, 1, init)
+    m = U.masks(prm)
+    for name, c in (("p", 3), ("u", 0), ("v", 1), ("w", 2)):
+        a, b = f.get_np(name), ref.get_np(name)
+        assert np.abs(a[m[c]] - b[m[c]]).max() <= 1e-13 * np.abs(b[m[c]]).max(), name
+    U.compare_state(f, o, prm, 1e-12)
+    assert abs(f.stats()["res_last"] - ref.stats()["res_last"]) <= 1e-13 * ref.stats()["res_last"]
+
+
+@pytest.mark.parametrize("tile", [(4, 16), (12, 0)])
+def test_fused_mixed_precision_shapes(tile):
+    prm = W.cavity(70, ny=24, nz=20, dt=0.002)
+    a = U.gpu_run(dict(prm, precision="mixed", tile=tile), 2)
+    b = U.gpu_run(dict(prm, precision="mixed", tile=(-1, 0)), 2)
+    o, _ = U.oracle_run(prm, 2)
+    m = U.masks(prm)
+    sc = U.velocity_scale([o.field(f) for f in "uvw"], prm)
+    for c, f in enumerate("uvw"):
+        assert U.vel_rel(a.get_np(f), b.get_np(f), m[c], sc) < 1e-6, f
+        assert U.vel_rel(a.get_np(f), o.field(f), m[c], sc) < 1e-5, f
+
+
+def test_autotuner_picks_a_valid_shape():
+    prm = W.cavity(160, ny=120, nz=128, dt=5e-4, itermax=3, tol=0.0)
+    from paper_1201_2118_amd.solver import Solver
+    s = Solver(prm)
+    t = s.timing()
+    assert t.sor_tile[0] in (4, 8, 12) and (t.sor_tile[1] == 0 or t.sor_tile[1] >= 8)
+    s.step(1)
+    o, _ = U.oracle_run(prm, 1)
+    U.compare_state(s, o, prm, 1e-12)
