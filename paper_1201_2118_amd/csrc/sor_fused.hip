@@ -74,10 +74,14 @@ k_sor_fused(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
   // Persistent loop over tiles.  Workgroup b runs on XCD b % 8; the tiles
   // are split into 8 contiguous ranges, one per XCD, dealt round-robin to
   // that XCD's workgroups, so the tiles in flight on one XCD are neighbours.
+  // (Fewer than 8 workgroups: plain strided order.)
   const int G = gridDim.x;
-  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int nwg_x = (G >> 3) + (xcd < (G & 7) ? 1 : 0);  // workgroups on this XCD
-  const int lo = (int)((long)ntiles * xcd / 8), hi = (int)((long)ntiles * (xcd + 1) / 8);
+  const bool by_xcd = G >= 8;
+  const int xcd = by_xcd ? (blockIdx.x & 7) : 0;
+  const int slot = by_xcd ? (blockIdx.x >> 3) : blockIdx.x;
+  const int nwg_x = by_xcd ? (G >> 3) + (xcd < (G & 7) ? 1 : 0) : G;  // workgroups on this XCD
+  const int lo = by_xcd ? (int)((long)ntiles * xcd / 8) : 0;
+  const int hi = by_xcd ? (int)((long)ntiles * (xcd + 1) / 8) : ntiles;
   for (int tile = lo + slot; tile < hi; tile += nwg_x) {
     const int bx = tile % ntx;
     const int rest = tile / ntx;
@@ -102,20 +106,30 @@ k_sor_fused(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
     const A w_mid = (A)(omega / (axy + 2.0 * g.idz2));
     const int cpar = (i + j) & 1;
 
-    auto plane = [&](int k) -> long { return (long)wrapc(k, g.nz, per2) * g.sxy + col; };
-    auto ldp = [&](int k) -> A { return zero_in ? A(0) : (A)p_in[plane(k)]; };
-    auto ldr = [&](int k) -> A { return halo1 ? (A)rhs[plane(k)] : A(0); };
+    // Loads are unconditional and their plane index is computed without
+    // branches, so no control flow separates a load from its use (the
+    // wait-count insertion would otherwise drain every load at the joins).
+    auto plane = [&](int k) -> long {
+      int kw = k + (per2 ? g.nz * ((k < 1) - (k > g.nz)) : 0);
+      kw = kw < 1 ? 1 : (kw > g.nz ? g.nz : kw);
+      return (long)kw * g.sxy + col;
+    };
+    auto ldp = [&](int k) -> A {
+      const A v = (A)p_in[plane(k)];  // p_in is a valid buffer even when zero_in
+      return zero_in ? A(0) : v;
+    };
+    auto ldr = [&](int k) -> A { return (A)rhs[plane(k)]; };
 
-    A pm2 = ldp(z0 - 2), pm1 = ldp(z0 - 1), p0 = ldp(z0), pn1 = ldp(z0 + 1);
-    A rh1 = ldr(z0 - 1), rq0 = ldr(z0);  // rhs at L-1 and L
-    A rh2 = A(0);                        // rhs at L-2
-    A rnA = A(0), rnB = A(0);            // new red values at L-3, L-2
+    // Register rings of 4 planes for the input and the rhs: at plane L the
+    // slots hold L-2, L-1, L, L+1 (the last two possibly still in flight);
+    // after the plane, the dead L-2 slot receives plane L+2.  The loop is
+    // unrolled by 4 so a loaded register is never moved (a move would wait
+    // for the load and cut the prefetch distance to one plane).
+    A P0 = ldp(z0 - 2), P1 = ldp(z0 - 1), P2 = ldp(z0), P3 = ldp(z0 + 1);
+    A R0 = A(0), R1 = ldr(z0 - 1), R2 = ldr(z0), R3 = ldr(z0 + 1);
+    A rnA = A(0), rnB = A(0);  // new red values at L-3, L-2
 
-    for (int L = z0; L <= z1 + 2; L++) {
-      // loads two planes ahead: input at L+2, rhs at L+1
-      const A pn2 = ldp(L + 2);
-      const A rq1 = ldr(L + 1);
-
+    auto body = [&](int L, A& pm2, A& pm1, A& p0, A& rh2, A& rh1) {
       sp[(L - 1) & 1][lid] = (T)pm1;
       lds_barrier();
 
@@ -159,15 +173,22 @@ k_sor_fused(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
         }
         if (write) p_out[(long)k2 * g.sxy + col] = (T)out;
       }
-      pm2 = pm1;
-      pm1 = p0;
-      p0 = pn1;
-      pn1 = pn2;
       rnA = rnB;
       rnB = rnew;
-      rh2 = rh1;
-      rh1 = rq0;
-      rq0 = rq1;
+      // refill the dead slots with plane L + 2
+      pm2 = ldp(L + 2);
+      rh2 = ldr(L + 2);
+    };
+
+    const int Lend = z1 + 2;
+    for (int L = z0; L <= Lend; L += 4) {
+      body(L, P0, P1, P2, R0, R1);
+      if (L + 1 > Lend) break;
+      body(L + 1, P1, P2, P3, R1, R2);
+      if (L + 2 > Lend) break;
+      body(L + 2, P2, P3, P0, R2, R3);
+      if (L + 3 > Lend) break;
+      body(L + 3, P3, P0, P1, R3, R0);
     }
     // the next tile reuses the LDS planes
     __syncthreads();
