@@ -38,6 +38,17 @@ __device__ __forceinline__ int wrapc(int i, int n, int per) {
   return i;
 }
 
+// Load / store at a uniform base plus a 32-bit per-lane byte offset (the
+// scalar-base addressing form: no 64-bit address per lane).
+template <class T>
+__device__ __forceinline__ T ld_off(const T* base, unsigned off) {
+  return *(const T*)((const char*)base + off);
+}
+template <class T>
+__device__ __forceinline__ void st_off(T* base, unsigned off, T v) {
+  *(T*)((char*)base + off) = v;
+}
+
 // Barrier that orders LDS only: global loads issued before it stay in
 // flight (a full __syncthreads would wait for them).
 __device__ __forceinline__ void lds_barrier() {
@@ -51,10 +62,12 @@ __device__ __forceinline__ void lds_barrier() {
 template <class T> struct Acc { using type = double; };
 template <> struct Acc<float> { using type = float; };
 
-template <class T, int TYH>
+// ZIN: the input iterate is identically zero (first sweep of a correction
+// solve); it is then never read.
+template <class T, int TYH, bool ZIN>
 __global__ void __launch_bounds__(kW * TYH)
 k_sor_fused(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restrict__ rhs, Geo g,
-            Ctl* ctl, double* part, double omega, int m, int itermax, int write, int zero_in, int inner,
+            Ctl* ctl, double* part, double omega, int m, int itermax, int write, int inner,
             int zc, int ntx, int nty, int ntiles) {
   using A = typename Acc<T>::type;
   constexpr int TY = TYH - 4;
@@ -92,6 +105,7 @@ k_sor_fused(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
     const int z0 = 1 + bz * zc;
     const int z1 = min(g.nz, z0 + zc - 1);
     const long col = (long)wrapc(j, g.ny, per1) * g.sx + wrapc(i, g.nx, per0);
+    const unsigned colb = (unsigned)col * (unsigned)sizeof(T);  // < one plane in bytes
     const bool own = tx >= 2 && tx <= kTX + 1 && ty >= 2 && ty <= TY + 1 && i <= g.nx && j <= g.ny;
 
     // boundary-eliminated coefficients in x and y (fixed per thread)
@@ -105,6 +119,7 @@ k_sor_fused(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
     const A w_lo = (A)(omega / (axy + az_lo));
     const A w_mid = (A)(omega / (axy + 2.0 * g.idz2));
     const int cpar = (i + j) & 1;
+    bool red_first = false;  // steady state: this thread's cell at plane L-1 is red
 
     // Loads are unconditional and their plane index is computed without
     // branches, so no control flow separates a load from its use (the
@@ -114,21 +129,20 @@ k_sor_fused(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
       kw = kw < 1 ? 1 : (kw > g.nz ? g.nz : kw);
       return (long)kw * g.sxy + col;
     };
-    auto ldp = [&](int k) -> A {
-      const A v = (A)p_in[plane(k)];  // p_in is a valid buffer even when zero_in
-      return zero_in ? A(0) : v;
-    };
+    auto ldp = [&](int k) -> A { return ZIN ? A(0) : (A)p_in[plane(k)]; };
     auto ldr = [&](int k) -> A { return (A)rhs[plane(k)]; };
 
     // Register rings of 4 planes for the input and the rhs: at plane L the
     // slots hold L-2, L-1, L, L+1 (the last two possibly still in flight);
-    // after the plane, the dead L-2 slot receives plane L+2.  The loop is
-    // unrolled by 4 so a loaded register is never moved (a move would wait
-    // for the load and cut the prefetch distance to one plane).
+    // after the plane, the dead L-2 slot receives plane L+2.  Bodies are
+    // called with the slots rotated, four per loop trip, so a loaded register
+    // is never moved (a move would wait for its load).
     A P0 = ldp(z0 - 2), P1 = ldp(z0 - 1), P2 = ldp(z0), P3 = ldp(z0 + 1);
     A R0 = A(0), R1 = ldr(z0 - 1), R2 = ldr(z0), R3 = ldr(z0 + 1);
     A rnA = A(0), rnB = A(0);  // new red values at L-3, L-2
 
+    // Generic plane: boundary coefficients, chunk limits and wrapped loads
+    // evaluated per plane.
     auto body = [&](int L, A& pm2, A& pm1, A& p0, A& rh2, A& rh1) {
       sp[(L - 1) & 1][lid] = (T)pm1;
       lds_barrier();
@@ -179,17 +193,96 @@ k_sor_fused(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
       pm2 = ldp(L + 2);
       rh2 = ldr(L + 2);
     };
-
-    const int Lend = z1 + 2;
-    for (int L = z0; L <= Lend; L += 4) {
+    // Up to four generic planes from L (a multiple of 4 past z0), stopping
+    // after plane `last`; returns the next plane.
+    auto gen_block = [&](int L, int last) -> int {
       body(L, P0, P1, P2, R0, R1);
-      if (L + 1 > Lend) break;
+      if (L + 1 > last) return L + 1;
       body(L + 1, P1, P2, P3, R1, R2);
-      if (L + 2 > Lend) break;
+      if (L + 2 > last) return L + 2;
       body(L + 2, P2, P3, P0, R2, R3);
-      if (L + 3 > Lend) break;
+      if (L + 3 > last) return L + 3;
       body(L + 3, P3, P0, P1, R3, R0);
+      return L + 4;
+    };
+
+    // Steady-state plane: both planes it touches are interior planes of the
+    // chunk and of the domain and its loads need no wrap, so the z
+    // coefficients are idz2, the relaxation factor is w_mid, and the load
+    // and store addresses advance by one plane per call from scalar bases.
+    // The LDS buffer of each call position is fixed for the loop.
+    const int parity = (z0 - 1) & 1;
+    T* const spA = sp[parity];
+    T* const spB = sp[parity ^ 1];
+    T* const srA = sr[parity];
+    T* const srB = sr[parity ^ 1];
+    const T* qp = nullptr;   // p_in at plane L + 2
+    const T* qr = nullptr;   // rhs at plane L + 2
+    T* qo = nullptr;         // p_out at plane L - 2
+    const A two = A(2);
+    auto fast = [&](T* spw, T* srw, T* srr, A& pm2, A& pm1, A& p0, A& rh2, A& rh1) {
+      spw[lid] = (T)pm1;
+      lds_barrier();
+      A rnew = pm1;
+      if (halo1) {
+        const A pc = pm1;
+        const A s = axm * ((A)spw[lid - 1] - pc) + axp * ((A)spw[lid + 1] - pc) +
+                    aym * ((A)spw[lid - kW] - pc) + ayp * ((A)spw[lid + kW] - pc) +
+                    idz2 * (pm2 + p0 - two * pc);
+        const A r = s - rh1;
+        if (own) acc += (double)r * (double)r;
+        if (red_first) rnew = (A)(T)(pc + w_mid * r);
+      }
+      srw[lid] = (T)rnew;
+      // the cell below a red cell is black: when this thread's cell at L-1
+      // is red, its cell at L-2 takes the black update; otherwise the cell
+      // at L-2 is red and was updated one plane ago
+      if (own) {
+        A out = rnB;
+        if (red_first) {
+          const A pc = pm2;
+          const A s = axm * ((A)srr[lid - 1] - pc) + axp * ((A)srr[lid + 1] - pc) +
+                      aym * ((A)srr[lid - kW] - pc) + ayp * ((A)srr[lid + kW] - pc) +
+                      idz2 * (rnA + rnew - two * pc);
+          out = pc + w_mid * (s - rh2);
+        }
+        if (write) st_off(qo, colb, (T)out);
+      }
+      rnA = rnB;
+      rnB = rnew;
+      // after a plane the colour of this thread's cell flips
+      red_first = !red_first;
+      pm2 = ZIN ? A(0) : (A)ld_off(qp, colb);
+      rh2 = (A)ld_off(qr, colb);
+      qp += g.sxy;
+      qr += g.sxy;
+      qo += g.sxy;
+    };
+
+    const int Lf0 = max(z0 + 2, per2 ? z0 + 2 : 4);
+    const int Lf1 = min(z1 + 1, g.nz - 2);
+    const int Lend = z1 + 2;
+    int L = z0;
+    while (L <= Lend && L < Lf0) L = gen_block(L, Lend);
+    if (L <= Lend && L + 3 <= Lf1) {
+      qp = p_in + (long)(L + 2) * g.sxy;
+      qr = rhs + (long)(L + 2) * g.sxy;
+      qo = p_out + (long)(L - 2) * g.sxy;
+      // colour of this thread's cell at plane L - 1 (red = even)
+      red_first = !((cpar + L - 1) & 1);
+      // Drain once here so that the loop header inherits no unknown pending
+      // loads from the generic planes (the wait-count pass would otherwise
+      // drain at every trip).
+      __builtin_amdgcn_s_waitcnt(0);
+      for (; L + 3 <= Lf1; L += 4) {
+        fast(spA, srA, srB, P0, P1, P2, R0, R1);
+        fast(spB, srB, srA, P1, P2, P3, R1, R2);
+        fast(spA, srA, srB, P2, P3, P0, R2, R3);
+        fast(spB, srB, srA, P3, P0, P1, R3, R0);
+      }
     }
+    // the epilogue resumes at a multiple of 4 past z0 (the ring phase)
+    while (L <= Lend) L = gen_block(L, Lend);
     // the next tile reuses the LDS planes
     __syncthreads();
   }
@@ -226,7 +319,8 @@ int resident_groups() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sor_fused<T, TYH>, kW * TYH, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sor_fused<T, TYH, false>, kW * TYH, 0) !=
+      hipSuccess)
     return 0;
   cached = cus * (per_cu > 0 ? per_cu : 1);
   return cached;
@@ -243,8 +337,12 @@ hipError_t launch_ty(hipStream_t st, const Geo& g, const T* p_in, T* p_out, cons
   const int ntiles = ntx * nty * ntz;
   int nb = resident_groups<T, TYH>();
   if (nb <= 0 || nb > ntiles) nb = ntiles;
-  k_sor_fused<T, TYH><<<nb, dim3(kW, TYH), 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write,
-                                                    zero_in, inner, zc, ntx, nty, ntiles);
+  if (zero_in)
+    k_sor_fused<T, TYH, true><<<nb, dim3(kW, TYH), 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax,
+                                                            write, inner, zc, ntx, nty, ntiles);
+  else
+    k_sor_fused<T, TYH, false><<<nb, dim3(kW, TYH), 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax,
+                                                             write, inner, zc, ntx, nty, ntiles);
   return hipGetLastError();
 }
 
