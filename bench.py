@@ -122,6 +122,11 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    ap.add_argument("--tile", type=int, nargs=2, default=None,
+                    help="fixed sweep shape (rows, z chunk) instead of the autotuned one")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="after the runs, copy this many GiB device-to-device once (a plain copy of "
+                         "known size that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the domain would be "
@@ -138,7 +143,10 @@ def main():
     res = {}
     for form in (["mixed", "fp64"] if args.only == "both" else [args.only]):
         log(f"{form}: {args.n}^3, warmup {args.warmup}, steps {args.steps}")
-        r = measure(dict(prm, precision=form), args.steps, args.warmup)
+        cfg = dict(prm, precision=form)
+        if args.tile:
+            cfg["tile"] = tuple(args.tile)
+        r = measure(cfg, args.steps, args.warmup)
         st = r["stats"]
         sweeps = st["sweeps_total"] / max(st["steps"], 1)
         r["alg_gbs"] = step_bytes(n, sweeps, form == "mixed", max(st["outer_max"], 1)) / (r["ms_per_step"] * 1e-3) / 1e9
@@ -179,6 +187,17 @@ def main():
                        "hbm_gbs_algorithmic": round(f["alg_gbs"], 1), "sor_gbs": round(f["sor_gbs"], 1),
                        "sor_avg_ms": round(f["sor_avg_ms"], 5), "tile": f["tile"],
                        "stage_ms": {k: round(v, 4) for k, v in f["stage_ms"].items()}}
+    if args.copy_probe > 0:
+        import torch
+        nbytes = int(args.copy_probe * (1 << 30))
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nbytes} bytes read, {nbytes} bytes written")
+        out["copy_probe_bytes"] = nbytes
+        del a, c
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(prm)

@@ -1,0 +1,97 @@
+"""GPU parity at the full sizes of the workloads, in the launch
+configuration the benchmark times (autotuned sweep shape).
+
+* 512^3 lid-driven cavity (Re 1000, dt 3e-4) from a seeded random velocity:
+  one step with exactly 2 sweeps (tol 0), every unknown of u, v, w, p
+  against the FP64 oracle -- FP64 to 1e-12, the FP32-mixed form against
+  the oracle running the same defect-correction schedule to 1e-5.
+* 64^3 adjoint workload (Re 400, dt 0.005, 20 steps, checkpoints every 5
+  steps, Gaussian initial velocity sigma 1e-2 seed 5, target from seed 6):
+  the gradient from ns_backward against central differences of the GPU
+  forward along 16 seeded unit directions (eps 1e-4), both solves to 1e-12,
+  each difference within 1e-5 of |grad|_2.
+"""
+import numpy as np
+import pytest
+
+import nsworkloads as W
+import oracle
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_start(prm, seed):
+    u, v, w = W.gaussian_velocity(prm, 0.05, seed)
+    return {"u": u, "v": v, "w": w}
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_cavity_512_two_sweeps_full_field(form):
+    prm, _ = W.cavity_512()
+    prm = dict(prm, tol=0.0, itermax=2)
+    init = _random_start(prm, 11)
+    s = U.gpu_run(dict(prm, precision=form), 1, init)
+    tile = list(s.timing().sor_tile)
+    o, rc = U.oracle_run(prm, 1, init, mode=0 if form == "fp64" else 1)
+    assert rc == 0
+    print(f"512^3 {form}: sweep shape {tile}", flush=True)
+    m = U.masks(prm)
+    ref = [o.field(f) for f in "uvw"]
+    scale = U.velocity_scale(ref, prm)
+    tol = 1e-12 if form == "fp64" else 1e-5
+    for c, f in enumerate("uvw"):
+        assert U.vel_rel(s.get_np(f), ref[c], m[c], scale) < tol, f
+    ptol = 1e-12 if form == "fp64" else 1e-4
+    assert U.pressure_rel(s.get_np("p"), o.p, m[3]) < ptol
+    assert s.stats()["sweeps_total"] == o.stats.sweeps_total == 2
+    if form == "fp64":
+        assert abs(s.stats()["res_last"] - o.stats.res_last) <= 1e-12 * o.stats.res_last
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_64_central_differences_16_directions():
+    prm, nsteps = W.adjoint_64()
+    # the adjoint is that of the exact solve: both solves run to 1e-12
+    prm = dict(prm, tol=1e-12, itermax=8000, checkpoint_every=5)
+    mk = [oracle.unknown_mask(prm, c) for c in range(3)]
+    u0 = [np.where(mk[c], f, 0.0) for c, f in enumerate(W.gaussian_velocity(prm, 1e-2, 5))]
+    seed6 = [np.where(mk[c], f, 0.0) for c, f in enumerate(W.gaussian_velocity(prm, 1e-2, 6))]
+    # target: a lid-speed-1 run from the independent seed-6 field
+    t = U.gpu_run(dict(prm, checkpoint_every=0), nsteps, {"u": seed6[0], "v": seed6[1], "w": seed6[2]})
+    tgt = [np.where(mk[c], t.get_np(f), 0.0) for c, f in enumerate("uvw")]
+    t.close()
+
+    from paper_1201_2118_amd.solver import Solver
+    fwd = dict(prm, checkpoint_every=0)
+
+    def loss(x):
+        s = Solver(fwd)
+        for f, a in zip("uvw", x):
+            s.set(f, a)
+        s.step(nsteps)
+        r = [np.where(mk[c], s.get_np(f) - tgt[c], 0.0) for c, f in enumerate("uvw")]
+        s.close()
+        return 0.5 * sum(float(np.sum(a * a)) for a in r)
+
+    s = U.gpu_run(prm, nsteps, {"u": u0[0], "v": u0[1], "w": u0[2]})
+    gf = [np.where(mk[c], s.get_np(f) - tgt[c], 0.0) for c, f in enumerate("uvw")]
+    grad = [g.cpu().numpy() for g in s.backward(gf)]
+    eps = 1e-4
+    # Directions are unit vectors, so each directional derivative is measured
+    # against |grad|_2: a direction nearly orthogonal to the gradient has a
+    # tiny derivative whose finite difference sits at the noise floor of the
+    # 1e-12 solves (about 1e-9 absolute here).
+    gnorm = np.sqrt(sum(float(np.sum(g * g)) for g in grad))
+    worst = 0.0
+    for k, d in enumerate(W.directions(prm, 16, 7)):
+        d = [np.where(mk[c], x, 0.0) for c, x in enumerate(d)]
+        nrm = np.sqrt(sum(float(np.sum(x * x)) for x in d))
+        d = [x / nrm for x in d]
+        fd = (loss([a + eps * b for a, b in zip(u0, d)]) - loss([a - eps * b for a, b in zip(u0, d)])) / (2 * eps)
+        an = sum(float(np.sum(g * x)) for g, x in zip(grad, d))
+        err = abs(fd - an) / gnorm
+        worst = max(worst, err)
+        print(f"direction {k}: fd {fd:.10e} adjoint {an:.10e} rel {err:.2e}", flush=True)
+    assert worst < 1e-5, worst
