@@ -77,6 +77,41 @@ def measure(prm, steps, warmup):
     }
 
 
+def measure_batched(steps):
+    """The batched workload: 64 cavities (sizes U{24..96}, Re U[50, 1000],
+    seed 4), adaptive dt (tau 0.5), FP32-mixed, one handle; one launch per
+    sweep covers all of them."""
+    import torch
+
+    import nsworkloads as W
+    from paper_1201_2118_amd import abi
+    from paper_1201_2118_amd.solver import Solver
+
+    prms, _ = W.batched_64()
+    prms = [dict(p, precision="mixed", flags=abi.NS_TIMING if i == 0 else 0) for i, p in enumerate(prms)]
+    s = Solver(prms, device="cuda:0")
+    s.step(1)
+    t0 = s.timing()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    t1 = s.timing()
+    cells = sum(p["nx"] * p["ny"] * p["nz"] for p in prms)
+    sweeps = sum(s.stats(i)["sweeps_total"] for i in range(len(prms)))
+    steps_done = sum(s.stats(i)["steps"] for i in range(len(prms)))
+    sor_ms = t1.ms[abi.NS_T_SOR] - t0.ms[abi.NS_T_SOR]
+    sor_bytes = t1.sor_bytes - t0.sor_bytes
+    tile = [t1.sor_tile[0], t1.sor_tile[1]]
+    s.close()
+    return {"value": round(cells * steps / (b - a) / 1e6, 2), "unit": "Mcell-steps/s", "instances": len(prms),
+            "cells": cells, "steps": steps, "ms_per_step": round((b - a) * 1e3 / steps, 3),
+            "mean_sweeps_per_instance_step": round(sweeps / steps_done, 1),
+            "sor_gbs": round(sor_bytes / (sor_ms * 1e-3) / 1e9, 1) if sor_ms > 0 else None, "tile": tile,
+            "precision": "mixed", "dt": "adaptive (tau 0.5)"}
+
+
 def step_bytes(n, sweeps, mixed, outers=1):
     """Algorithmic HBM bytes of one step per cell (minimum single pass per
     stage): FP64 112 + 24 S; mixed 60 + 12 S + 28 O."""
@@ -124,6 +159,8 @@ def main():
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument("--tile", type=int, nargs=2, default=None,
                     help="fixed sweep shape (rows, z chunk) instead of the autotuned one")
+    ap.add_argument("--batched-steps", type=int, default=10,
+                    help="steps of the 64-cavity batched workload to time (0 = skip)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="after the runs, copy this many GiB device-to-device once (a plain copy of "
                          "known size that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -187,6 +224,9 @@ def main():
                        "hbm_gbs_algorithmic": round(f["alg_gbs"], 1), "sor_gbs": round(f["sor_gbs"], 1),
                        "sor_avg_ms": round(f["sor_avg_ms"], 5), "tile": f["tile"],
                        "stage_ms": {k: round(v, 4) for k, v in f["stage_ms"].items()}}
+    if args.batched_steps > 0:
+        out["batched"] = measure_batched(args.batched_steps)
+        log(f"batched: {out['batched']['value']} Mcell-steps/s over {out['batched']['instances']} cavities")
     if args.copy_probe > 0:
         import torch
         nbytes = int(args.copy_probe * (1 << 30))

@@ -98,6 +98,26 @@ bool fused_shape_ok(const SorShape& s);
 int fused_resident(int ty, bool f32);       // workgroups resident on the device at once
 int fused_columns(const Geo& g, int ty);    // x-y tiles of one z chunk
 
+// One domain of a batched sweep (device-resident table, sorted by `first`).
+struct BatchItem {
+  Geo g;
+  void* p[2];      // iterate buffers; sweep m reads p[(cur + m - 1) & 1], writes p[(cur + m) & 1]
+  const void* rhs;
+  Ctl* ctl;
+  double* part;
+  double omega;
+  int cur;
+  int first;       // first workgroup of this domain
+  int ntiles, ntx, nty, zc;
+  int budget;      // the solve stops at iterate `budget` at the latest
+  int inner;       // 1: correction solve (stop at ctl->thr_in)
+};
+// Fill ntx, nty, zc and ntiles of an item for a sweep shape.
+void batch_item_shape(BatchItem& it, int ty, int zc);
+// One sweep of every domain of a batch in one launch (nblocks = sum of ntiles).
+template <class T> hipError_t launch_sor_batched(hipStream_t st, const BatchItem* d_items, int nitems,
+                                                int nblocks, int ty, int m, int write, int zero_in);
+
 // Adjoint of the predictor in gather form (FP64 only): z = B^T J_Phi(u)^T mu.
 hipError_t launch_adj_fgh(hipStream_t st, const Geo& g, const double* u, const double* v,
                           const double* w, const double* mu, const double* mv, const double* mw,

@@ -88,6 +88,12 @@ struct ns_solver {
   std::vector<EvRec> recs;
   double* stage = nullptr;  // FP64 staging buffer for conversions
   size_t stage_n = 0;
+  Ctl* ctl_all = nullptr;   // control blocks of all instances, contiguous
+  // batched sweeps (several instances of one precision)
+  bool batched = false;
+  int batch_ty = 8, batch_zc = 0;
+  BatchItem* items_h = nullptr;  // pinned
+  BatchItem* items_d = nullptr;
 };
 
 namespace {
@@ -301,6 +307,71 @@ ns_status autotune(ns_solver* s, Inst& I) {
   return NS_OK;
 }
 
+// Batch shape: time rows 4 / 8 / 12 x z chunk whole / 32 / 16 with one
+// batched sweep each over all instances (zero buffers, a scratch control
+// array that never converges), keep the fastest.
+template <class T>
+ns_status tune_batch_run(ns_solver* s, Ctl* tctl, int ty, int zc, float* ms) {
+  const int n = (int)s->in.size();
+  int nblocks = 0;
+  for (int i = 0; i < n; i++) {
+    Inst& I = s->in[i];
+    BatchItem& it = s->items_h[i];
+    it.g = I.g;
+    it.p[0] = I.mixed ? (void*)I.e[0] : (void*)I.s.p[0];
+    it.p[1] = I.mixed ? (void*)I.e[1] : (void*)I.s.p[1];
+    it.rhs = I.mixed ? (const void*)I.r : (const void*)I.rhs;
+    it.ctl = tctl + i;
+    it.part = I.part;
+    it.omega = I.prm.omega;
+    it.cur = 0;
+    it.budget = 1 << 30;
+    it.inner = 0;
+    batch_item_shape(it, ty, zc);
+    it.first = nblocks;
+    nblocks += it.ntiles;
+  }
+  HCK(s, hipMemcpyAsync(s->items_d, s->items_h, sizeof(BatchItem) * n, hipMemcpyHostToDevice, s->stream));
+  hipEvent_t a, b;
+  HCK(s, hipEventCreate(&a));
+  HCK(s, hipEventCreate(&b));
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < 4 && e == hipSuccess; it++) {
+    if (it == 1) e = hipEventRecord(a, s->stream);
+    if (e == hipSuccess) e = launch_sor_batched<T>(s->stream, s->items_d, n, nblocks, ty, 1, 1, 0);
+  }
+  if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail_hip(s, "batch autotune", e);
+  return NS_OK;
+}
+
+ns_status autotune_batch(ns_solver* s) {
+  const int n = (int)s->in.size();
+  Ctl* tctl = nullptr;
+  HCK(s, dmalloc((void**)&tctl, sizeof(Ctl) * n));
+  const int rows[3] = {4, 8, 12};
+  const int zcs[3] = {0, 32, 16};
+  float best = 1e30f;
+  ns_status st = NS_OK;
+  for (int r = 0; r < 3 && st == NS_OK; r++)
+    for (int z = 0; z < 3 && st == NS_OK; z++) {
+      float ms = 0.f;
+      st = s->in[0].mixed ? tune_batch_run<float>(s, tctl, rows[r], zcs[z], &ms)
+                          : tune_batch_run<double>(s, tctl, rows[r], zcs[z], &ms);
+      if (st == NS_OK && ms < best) {
+        best = ms;
+        s->batch_ty = rows[r];
+        s->batch_zc = zcs[z];
+      }
+    }
+  (void)hipFree(tctl);
+  return st;
+}
+
 hipError_t dmalloc(void** p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) { *p = nullptr; return e; }
@@ -318,7 +389,7 @@ void free_inst(Inst& I) {
   (void)hipFree(I.F); (void)hipFree(I.G); (void)hipFree(I.H); (void)hipFree(I.rhs);
   for (int c = 0; c < 3; c++) (void)hipFree(I.frc[c]);
   (void)hipFree(I.e[0]); (void)hipFree(I.e[1]); (void)hipFree(I.r);
-  (void)hipFree(I.part); (void)hipFree(I.ctl);
+  (void)hipFree(I.part);  // I.ctl lives in the handle's ctl_all
   for (auto& c : I.ck) free_state(c);
   I.ck.clear();
   free_state(I.R);
@@ -486,8 +557,9 @@ ns_status solve_mixed(ns_solver* s, int idx, int* sweeps, int* outer) {
 }
 
 // ---- one step ------------------------------------------------------------------
+// Stages before the Poisson solve: dt, boundary fill, predictor, rhs.
 template <class T>
-ns_status step_inst(ns_solver* s, int idx, State& S, bool account) {
+ns_status step_pre(ns_solver* s, int idx, State& S) {
   Inst& I = s->in[idx];
   const Geo& g = I.g;
   const ns_params& p = I.prm;
@@ -512,14 +584,19 @@ ns_status step_inst(ns_solver* s, int idx, State& S, bool account) {
     HCK(s, launch_rhs<T>(s->stream, g, (const T*)I.F, (const T*)I.G, (const T*)I.H, (T*)I.rhs, I.ctl, I.part,
                          p.tol, 0.0));
   }
-  int sweeps = 0, outer = 0;
-  ns_status e;
-  if (I.mixed) {
-    e = solve_mixed(s, idx, &sweeps, &outer);
-  } else {
-    e = solve_fp64(s, idx, S.p, &S.pcur, &sweeps);
-  }
-  if (e != NS_OK) return e;
+  return NS_OK;
+}
+
+// Stages after the solve: pressure ghosts, projection, boundary fill; then
+// the statistics from the last polled control block.
+template <class T>
+ns_status step_post(ns_solver* s, int idx, State& S, int sweeps, int outer, bool account) {
+  Inst& I = s->in[idx];
+  const Geo& g = I.g;
+  const ns_params& p = I.prm;
+  T* u = (T*)S.u;
+  T* v = (T*)S.v;
+  T* w = (T*)S.w;
   const Ctl h = s->hctl[idx];
   {
     Timed t(s, NS_T_PROJECT);
@@ -530,10 +607,6 @@ ns_status step_inst(ns_solver* s, int idx, State& S, bool account) {
   {
     Timed t(s, NS_T_BC);
     HCK(s, launch_bc_vel<T>(s->stream, g, u, v, w, p.wall_vel));
-  }
-  if (s->timing) {
-    HCK(s, hipStreamSynchronize(s->stream));
-    harvest(s, I.mixed ? 1 << 30 : sweeps + 1);
   }
   if (h.nonfinite) return fail(s, NS_E_NONFINITE, "non-finite residual in the pressure solve");
   if (account) {
@@ -548,6 +621,187 @@ ns_status step_inst(ns_solver* s, int idx, State& S, bool account) {
     st.steps++;
   }
   return NS_OK;
+}
+
+template <class T>
+ns_status step_inst(ns_solver* s, int idx, State& S, bool account) {
+  Inst& I = s->in[idx];
+  ns_status e = step_pre<T>(s, idx, S);
+  if (e != NS_OK) return e;
+  int sweeps = 0, outer = 0;
+  e = I.mixed ? solve_mixed(s, idx, &sweeps, &outer) : solve_fp64(s, idx, S.p, &S.pcur, &sweeps);
+  if (e != NS_OK) return e;
+  e = step_post<T>(s, idx, S, sweeps, outer, account);
+  if (s->timing) {
+    HCK(s, hipStreamSynchronize(s->stream));
+    harvest(s, I.mixed ? 1 << 30 : sweeps + 1);
+  }
+  return e;
+}
+
+// ---- batched solves ------------------------------------------------------------
+// Every domain of the handle is swept by one launch per sweep
+// (launch_sor_batched); each domain keeps its own stop rule, budget and done
+// flag, and the host reads all control blocks with one copy per chunk.
+ns_status poll_all(ns_solver* s) {
+  HCK(s, hipMemcpyAsync(s->hctl, s->ctl_all, sizeof(Ctl) * s->in.size(), hipMemcpyDeviceToHost, s->stream));
+  HCK(s, hipStreamSynchronize(s->stream));
+  return NS_OK;
+}
+
+// Runs launches m = 1, 2, ... over the items in s->items_h[0..n) until every
+// item is done; bpc = algorithmic bytes per cell of one sweep.
+template <class T>
+ns_status run_batched(ns_solver* s, int n, int max_budget, int pred, int zero_first, long long bpc,
+                      const std::vector<int>& idx_of_item) {
+  int nblocks = 0;
+  long long cells = 0;
+  for (int q = 0; q < n; q++) {
+    BatchItem& it = s->items_h[q];
+    it.first = nblocks;
+    nblocks += it.ntiles;
+    cells += (long long)it.g.nx * it.g.ny * it.g.nz;
+  }
+  HCK(s, hipMemcpyAsync(s->items_d, s->items_h, sizeof(BatchItem) * n, hipMemcpyHostToDevice, s->stream));
+  const size_t rec0 = s->recs.size();
+  int m = 0;
+  bool first = true;
+  for (;;) {
+    const int chunk = first ? std::min(std::max(pred + 2, 4), max_budget + 1) : std::max(4, pred / 4);
+    first = false;
+    for (int c = 0; c < chunk && m < max_budget + 1; c++) {
+      m++;
+      Timed t(s, NS_T_SOR, 2000000 + m, bpc * cells);
+      HCK(s, launch_sor_batched<T>(s->stream, s->items_d, n, nblocks, s->batch_ty, m, 1,
+                                   zero_first && m == 1));
+    }
+    ns_status e = poll_all(s);
+    if (e != NS_OK) return e;
+    bool all = true;
+    for (int q = 0; q < n; q++) all &= s->hctl[idx_of_item[q]].done != 0;
+    if (all) break;
+    if (m >= max_budget + 1) return fail(s, NS_E_DEVICE, "batched solve ended without a decision");
+  }
+  // algorithmic bytes of each launch: the domains that still swept in it
+  for (size_t q = rec0; q < s->recs.size(); q++) {
+    EvRec& rc = s->recs[q];
+    if (rc.stage != NS_T_SOR || rc.m < 2000000) continue;
+    const int mm = rc.m - 2000000;
+    long long by = 0;
+    for (int it = 0; it < n; it++) {
+      const BatchItem& bi = s->items_h[it];
+      if (s->hctl[idx_of_item[it]].final_ + 1 >= mm) by += bpc * (long long)bi.g.nx * bi.g.ny * bi.g.nz;
+    }
+    if (by == 0) rc.stage = NS_T_COUNT - 1;  // every domain had returned on its flag
+    else rc.bytes = by;
+  }
+  return NS_OK;
+}
+
+void fill_item(ns_solver* s, BatchItem& it, Inst& I, void* p0, void* p1, const void* rhs, int cur, int budget,
+               int inner) {
+  it.g = I.g;
+  it.p[0] = p0;
+  it.p[1] = p1;
+  it.rhs = rhs;
+  it.ctl = I.ctl;
+  it.part = I.part;
+  it.omega = I.prm.omega;
+  it.cur = cur;
+  it.budget = budget;
+  it.inner = inner;
+  batch_item_shape(it, s->batch_ty, s->batch_zc);
+}
+
+ns_status solve_batched_fp64(ns_solver* s, std::vector<int>& sweeps) {
+  const int n = (int)s->in.size();
+  int max_budget = 0, pred = 0;
+  std::vector<int> ids(n);
+  for (int i = 0; i < n; i++) {
+    Inst& I = s->in[i];
+    fill_item(s, s->items_h[i], I, I.s.p[0], I.s.p[1], I.rhs, I.s.pcur, I.prm.itermax, 0);
+    max_budget = std::max(max_budget, I.prm.itermax);
+    pred = std::max(pred, I.pred);
+    ids[i] = i;
+  }
+  ns_status e = run_batched<double>(s, n, max_budget, pred, 0, 24, ids);
+  if (e != NS_OK) return e;
+  for (int i = 0; i < n; i++) {
+    Inst& I = s->in[i];
+    const int f = s->hctl[i].final_;
+    sweeps[i] = f;
+    I.s.pcur = (I.s.pcur + f) & 1;
+    I.pred = f;
+  }
+  return NS_OK;
+}
+
+ns_status solve_batched_mixed(ns_solver* s, std::vector<int>& sweeps, std::vector<int>& outer) {
+  const int n = (int)s->in.size();
+  const long long big = 1;
+  (void)big;
+  for (int i = 0; i < n; i++) {
+    Inst& I = s->in[i];
+    sweeps[i] = 0;
+    outer[i] = 0;
+    Timed t(s, NS_T_DEFECT, 0, 20LL * I.g.nx * I.g.ny * I.g.nz);
+    HCK(s, launch_defect(s->stream, I.g, I.s.p[I.s.pcur], nullptr, nullptr, (const float*)I.rhs, I.r, I.ctl,
+                         I.part, I.prm.eta));
+  }
+  for (;;) {
+    ns_status e = poll_all(s);
+    if (e != NS_OK) return e;
+    std::vector<int> ids;
+    int max_budget = 0, pred = 0;
+    for (int i = 0; i < n; i++) {
+      Inst& I = s->in[i];
+      const Ctl& h = s->hctl[i];
+      if (h.outer_done || h.nonfinite || sweeps[i] >= I.prm.itermax) continue;
+      const int budget = I.prm.itermax - sweeps[i];
+      fill_item(s, s->items_h[ids.size()], I, I.e[0], I.e[1], I.r, 0, budget, 1);
+      ids.push_back(i);
+      outer[i]++;
+      max_budget = std::max(max_budget, budget);
+      pred = std::max(pred, I.pred);
+    }
+    if (ids.empty()) break;
+    e = run_batched<float>(s, (int)ids.size(), max_budget, pred, 1, 12, ids);
+    if (e != NS_OK) return e;
+    for (int q = 0; q < (int)ids.size(); q++) {
+      const int i = ids[q];
+      Inst& I = s->in[i];
+      const int f = s->hctl[i].final_;
+      sweeps[i] += f;
+      I.pred = f;
+      Timed t(s, NS_T_DEFECT, 0, 40LL * I.g.nx * I.g.ny * I.g.nz);
+      HCK(s, launch_defect(s->stream, I.g, I.s.p[I.s.pcur], I.e[f & 1], I.s.p[I.s.pcur ^ 1], (const float*)I.rhs,
+                           I.r, I.ctl, I.part, I.prm.eta));
+      I.s.pcur ^= 1;
+    }
+  }
+  return NS_OK;
+}
+
+template <class T>
+ns_status step_batched(ns_solver* s) {
+  const int n = (int)s->in.size();
+  for (int i = 0; i < n; i++) {
+    ns_status e = step_pre<T>(s, i, s->in[i].s);
+    if (e != NS_OK) return e;
+  }
+  std::vector<int> sweeps(n, 0), outer(n, 0);
+  ns_status e = s->in[0].mixed ? solve_batched_mixed(s, sweeps, outer) : solve_batched_fp64(s, sweeps);
+  if (e != NS_OK) return e;
+  ns_status ret = NS_OK;
+  for (int i = 0; i < n; i++) {
+    e = step_post<T>(s, i, s->in[i].s, sweeps[i], outer[i], true);
+    if (e != NS_OK && ret == NS_OK) ret = e;
+  }
+  if (s->timing) {
+    HCK(s, hipStreamSynchronize(s->stream));
+    harvest(s, 1 << 30);
+  }
+  return ret;
 }
 
 ns_status copy_in(ns_solver* s, Inst& I, void* dst, bool dst_f32, const double* src, int on_device) {
@@ -642,6 +896,8 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
   if (hipHostMalloc((void**)&s->hctl, sizeof(Ctl) * n_instances, hipHostMallocDefault) != hipSuccess)
     return bail(NS_E_OOM, "pinned control block allocation failed");
   memset(s->hctl, 0, sizeof(Ctl) * n_instances);
+  if (dmalloc((void**)&s->ctl_all, sizeof(Ctl) * n_instances) != hipSuccess)
+    return bail(NS_E_OOM, "control block allocation failed");
   size_t max_ntot = 0;
   for (int i = 0; i < n_instances; i++) {
     Inst& I = s->in[i];
@@ -663,7 +919,7 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
       if (e == hipSuccess) e = dmalloc((void**)&I.r, (size_t)I.g.ntot * 4);
     }
     if (e == hipSuccess) e = dmalloc((void**)&I.part, reduce_blocks(I.g) * sizeof(double));
-    if (e == hipSuccess) e = dmalloc((void**)&I.ctl, sizeof(Ctl));
+    I.ctl = s->ctl_all + i;
     if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? NS_E_OOM : NS_E_DEVICE,
                                      std::string("allocation failed: ") + hipGetErrorString(e));
     Ctl c{};
@@ -690,8 +946,26 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
     if (e != hipSuccess) return bail(NS_E_DEVICE, std::string("boundary fill failed: ") + hipGetErrorString(e));
   }
   if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(NS_E_DEVICE, "stream synchronisation failed");
-  for (auto& I : s->in) {
-    if (autotune(s, I) != NS_OK) return bail(NS_E_DEVICE, "autotune: " + s->err);
+  // several instances of one precision: one launch per sweep for all of them
+  {
+    bool same = n_instances > 1;
+    for (auto& I : s->in) same &= I.mixed == s->in[0].mixed && I.prm.tile[0] >= 0;
+    s->batched = same;
+  }
+  if (s->batched) {
+    if (hipHostMalloc((void**)&s->items_h, sizeof(BatchItem) * n_instances, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&s->items_d, sizeof(BatchItem) * n_instances) != hipSuccess)
+      return bail(NS_E_OOM, "batch table allocation failed");
+    if (params[0].tile[0] > 0) {
+      s->batch_ty = params[0].tile[0];
+      s->batch_zc = params[0].tile[1];
+    } else if (autotune_batch(s) != NS_OK) {
+      return bail(NS_E_DEVICE, "batch autotune: " + s->err);
+    }
+  } else {
+    for (auto& I : s->in) {
+      if (autotune(s, I) != NS_OK) return bail(NS_E_DEVICE, "autotune: " + s->err);
+    }
   }
   // the trial sweeps wrote the second pressure buffer: clear it again
   for (auto& I : s->in)
@@ -774,19 +1048,32 @@ ns_status ns_step(ns_solver* s, int32_t nsteps, ns_stats* stats) {
   if (nsteps < 0) return fail(s, NS_E_INVALID, "nsteps must be >= 0");
   DevGuard dg(s->device);
   ns_status ret = NS_OK;
+  auto checkpoint = [&](Inst& I) -> ns_status {
+    const int k = I.prm.checkpoint_every;
+    if (!(k > 0 && I.rec_valid && I.rec_steps % k == 0)) return NS_OK;
+    const size_t slot = I.rec_steps / k;
+    while (I.ck.size() <= slot) {
+      I.ck.emplace_back();
+      hipError_t e = alloc_state(I.ck.back(), I);
+      if (e != hipSuccess) return fail_hip(s, "checkpoint allocation", e);
+    }
+    return save_state(s, I, I.s, I.ck[slot]);
+  };
   for (int n = 0; n < nsteps && ret == NS_OK; n++) {
+    if (s->batched) {
+      for (auto& I : s->in)
+        if (ret == NS_OK) ret = checkpoint(I);
+      if (ret == NS_OK) ret = s->in[0].mixed ? step_batched<float>(s) : step_batched<double>(s);
+      for (auto& I : s->in) {
+        if (ret == NS_OK && I.prm.checkpoint_every > 0 && I.rec_valid) I.rec_steps++;
+        if (ret != NS_OK) I.rec_valid = false;
+      }
+      continue;
+    }
     for (int i = 0; i < (int)s->in.size() && ret == NS_OK; i++) {
       Inst& I = s->in[i];
       const int k = I.prm.checkpoint_every;
-      if (k > 0 && I.rec_valid && I.rec_steps % k == 0) {
-        const size_t slot = I.rec_steps / k;
-        while (I.ck.size() <= slot) {
-          I.ck.emplace_back();
-          hipError_t e = alloc_state(I.ck.back(), I);
-          if (e != hipSuccess) { ret = fail_hip(s, "checkpoint allocation", e); break; }
-        }
-        if (ret == NS_OK) ret = save_state(s, I, I.s, I.ck[slot]);
-      }
+      ret = checkpoint(I);
       if (ret != NS_OK) break;
       ret = I.mixed ? step_inst<float>(s, i, I.s, true) : step_inst<double>(s, i, I.s, true);
       if (ret == NS_OK && k > 0 && I.rec_valid) I.rec_steps++;
@@ -801,8 +1088,8 @@ ns_status ns_step(ns_solver* s, int32_t nsteps, ns_stats* stats) {
 ns_status ns_get_timing(const ns_solver* s, ns_timing* out) {
   if (!s || !out) return fail(const_cast<ns_solver*>(s), NS_E_INVALID, "NULL argument");
   *out = s->tm;
-  out->sor_tile[0] = s->in[0].shape.ty;
-  out->sor_tile[1] = s->in[0].shape.zc;
+  out->sor_tile[0] = s->batched ? s->batch_ty : s->in[0].shape.ty;
+  out->sor_tile[1] = s->batched ? s->batch_zc : s->in[0].shape.zc;
   return NS_OK;
 }
 
@@ -907,6 +1194,9 @@ void ns_destroy(ns_solver* s) {
   for (auto& I : s->in) free_inst(I);
   for (auto e : s->pool) (void)hipEventDestroy(e);
   if (s->hctl) (void)hipHostFree(s->hctl);
+  if (s->items_h) (void)hipHostFree(s->items_h);
+  (void)hipFree(s->items_d);
+  (void)hipFree(s->ctl_all);
   (void)hipFree(s->stage);
   delete s;
 }

@@ -125,15 +125,56 @@ def test_restart_and_determinism_are_bitwise():
         assert np.array_equal(a.get_np(f), d.get_np(f)), f
 
 
-def test_several_instances_match_standalone_runs():
-    prms = [W.cavity(10, ny=12, nz=8), W.cavity(16, re=300.0, dt=0.004), W.periodic_box(8, nz=6, dt=1e-3)]
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_batched_instances_match_standalone_runs_and_oracle(form):
+    """Several domains in one handle share one launch per sweep; each keeps
+    its own stop rule, so it equals its standalone run (same sweep counts,
+    fields to rounding: the sweep shapes differ) and the oracle."""
+    prms = [W.cavity(10, ny=12, nz=8), W.cavity(16, re=300.0, dt=0.004), W.periodic_box(8, nz=6, dt=1e-3),
+            W.cavity(37, ny=25, nz=30, re=700.0, dt=0.0, tau=0.5), W.cavity(61, ny=9, nz=14, re=90.0, dt=0.0)]
+    prms = [dict(p, precision=form) for p in prms]
     from paper_1201_2118_amd.solver import Solver
     s = Solver(prms)
     s.step(3)
     for i, prm in enumerate(prms):
         one = U.gpu_run(prm, 3)
-        for f in "uvwp":
-            assert np.array_equal(s.get_np(f, i), one.get_np(f)), (i, f)
+        st, so = s.stats(i), one.stats()
+        assert st["sweeps_total"] == so["sweeps_total"], (i, st, so)
+        assert st["t"] == so["t"]
+        m = U.masks(prm)
+        ref = [one.get_np(f) for f in "uvw"]
+        sc = U.velocity_scale(ref, prm)
+        # different sweep shapes round differently (FP32 arithmetic in the
+        # mixed correction sweeps)
+        same = 1e-13 if form == "fp64" else 1e-6
+        for c, f in enumerate("uvw"):
+            assert U.vel_rel(s.get_np(f, i), ref[c], m[c], sc) < same, (i, f)
+        o, _ = U.oracle_run(dict(prm, precision="fp64"), 3, mode=0 if form == "fp64" else 1)
+        so = U.velocity_scale([o.field(f) for f in "uvw"], prm)
+        for c, f in enumerate("uvw"):
+            assert U.vel_rel(s.get_np(f, i), o.field(f), m[c], so) < (1e-12 if form == "fp64" else 1e-5), (i, f)
+
+
+def test_batched_workload_runs():
+    """The 64-cavity workload (sizes U{24..96}, Re U[50, 1000], adaptive dt,
+    mixed precision), a few steps: every instance advances and stays
+    finite; two instances are checked against standalone runs."""
+    prms, _ = W.batched_64()
+    prms = [dict(p, precision="mixed") for p in prms]
+    from paper_1201_2118_amd.solver import Solver
+    s = Solver(prms)
+    s.step(2)
+    for i in range(len(prms)):
+        st = s.stats(i)
+        assert st["steps"] == 2 and st["dt_last"] > 0 and np.isfinite(st["res_last"])
+    for i in (0, 41):
+        one = U.gpu_run(prms[i], 2)
+        assert s.stats(i)["sweeps_total"] == one.stats()["sweeps_total"]
+        m = U.masks(prms[i])
+        ref = [one.get_np(f) for f in "uvw"]
+        sc = U.velocity_scale(ref, prms[i])
+        for c, f in enumerate("uvw"):
+            assert U.vel_rel(s.get_np(f, i), ref[c], m[c], sc) < 1e-6, (i, f)
 
 
 def test_nonfinite_state_is_reported():
