@@ -97,10 +97,16 @@ typedef struct {
   int32_t precision;      /* NS_FP64 or NS_MIXED */
   int32_t checkpoint_every; /* > 0: record checkpoints every k steps for ns_backward */
   int32_t flags;          /* NS_ALLOW_UNSTABLE | NS_TIMING */
-  int32_t tile[2];        /* fused SOR sweep shape: {rows per workgroup (4, 8 or 12),
-                             z planes per chunk (0 = whole column)}; {0, 0} = chosen by the
-                             autotuner; rows = -1 selects the unfused one-pass-per-colour
-                             sweeps (reference path). Results do not depend on it. */
+  int32_t tile[2];        /* SOR sweep shape: {rows, z planes per chunk (0 = whole column)}.
+                             rows 4, 8 or 12: one sweep per launch, that many interior rows
+                             per workgroup; rows 16, 24 or 32: two sweeps per launch
+                             (temporal blocking), that many rows per workgroup including a
+                             4-row halo on each side (periodic axes need >= 4 cells);
+                             {0, 0} = chosen by the autotuner; rows = -1 selects the unfused
+                             one-pass-per-colour sweeps (reference path). The fused shapes
+                             address a plane with 31-bit byte offsets: larger planes need
+                             rows = -1. Sweep counts and iterates do not depend on it beyond
+                             rounding. */
 } ns_params;
 
 typedef struct {

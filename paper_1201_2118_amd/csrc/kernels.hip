@@ -24,21 +24,6 @@ inline int grid_for(long n, int cap = 8192) {
   return (int)(b < cap ? b : cap);
 }
 
-// Flattened interior-cell loop: t -> (i, j, k) in [1, nx] x [1, ny] x [1, nz].
-struct Cell {
-  int i, j, k;
-  long c;
-};
-__device__ __forceinline__ Cell cell_of(const Geo& g, long t) {
-  Cell r;
-  long row = t / g.nx;
-  r.i = (int)(t - row * g.nx) + 1;
-  r.k = (int)(row / g.ny) + 1;
-  r.j = (int)(row - (long)(r.k - 1) * g.ny) + 1;
-  r.c = (long)r.k * g.sxy + (long)r.j * g.sx + r.i;
-  return r;
-}
-
 // ---------------------------------------------------------------------------
 // Ghost / boundary fill.  Walls: wall-normal faces := 0 (full extent), then
 // tangential ghosts := 2 U_wall - adjacent interior (interior extent of the
@@ -188,17 +173,14 @@ __device__ __forceinline__ double flux(double t, double a, double b, double gamm
 
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_fgh(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
+k_fgh(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
       const T* __restrict__ fx, const T* __restrict__ fy, const T* __restrict__ fz,
       T* __restrict__ F, T* __restrict__ G, T* __restrict__ H, Geo g, const Ctl* __restrict__ ctl,
       double nu, double gamma, double gx, double gy, double gz) {
   const double dt = ctl->dt;
-  const long n = (long)g.nx * g.ny * g.nz;
   const long sx = g.sx, sxy = g.sxy;
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    const Cell cl = cell_of(g, t);
-    const long c = cl.c;
-    if (cl.i <= g.hi[0]) {  // F on the x face i
+  for_cells(g, zr, [&](int ci, int cj, int ck, long c) {
+    if (ci <= g.hi[0]) {  // F on the x face i
       const double q = u[c], qe = u[c + 1], qw = u[c - 1], qn = u[c + sx], qs = u[c - sx],
                    qt = u[c + sxy], qb = u[c - sxy];
       const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
@@ -213,7 +195,7 @@ k_fgh(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
       const double f = gx + (fx ? (double)fx[c] : 0.0);
       F[c] = T(q + dt * (nu * lap - cx - cy - cz + f));
     }
-    if (cl.j <= g.hi[1]) {  // G on the y face j
+    if (cj <= g.hi[1]) {  // G on the y face j
       const double q = v[c], qe = v[c + 1], qw = v[c - 1], qn = v[c + sx], qs = v[c - sx],
                    qt = v[c + sxy], qb = v[c - sxy];
       const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
@@ -228,7 +210,7 @@ k_fgh(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
       const double f = gy + (fy ? (double)fy[c] : 0.0);
       G[c] = T(q + dt * (nu * lap - cx - cy - cz + f));
     }
-    if (cl.k <= g.hi[2]) {  // H on the z face k
+    if (ck <= g.hi[2]) {  // H on the z face k
       const double q = w[c], qe = w[c + 1], qw = w[c - 1], qn = w[c + sx], qs = w[c - sx],
                    qt = w[c + sxy], qb = w[c - sxy];
       const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
@@ -243,7 +225,7 @@ k_fgh(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
       const double f = gz + (fz ? (double)fz[c] : 0.0);
       H[c] = T(q + dt * (nu * lap - cx - cy - cz + f));
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -254,29 +236,29 @@ k_fgh(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
 // adjoint projection).
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_rhs(const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
+k_rhs(int zr, const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
       T* __restrict__ rhs, Geo g, Ctl* ctl, double* part, double tol, int unit_dt) {
   __shared__ double sh[16];
   __shared__ int sh_last;
   const double idt = unit_dt ? 1.0 : 1.0 / ctl->dt;
   const long n = (long)g.nx * g.ny * g.nz;
   double acc = 0.0;
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    const Cell cl = cell_of(g, t);
-    const long c = cl.c;
-    const long cw = (cl.i > 1 || !g.per[0]) ? c - 1 : c + (g.nx - 1);
-    const long cs = (cl.j > 1 || !g.per[1]) ? c - g.sx : c + (long)(g.ny - 1) * g.sx;
-    const long cb = (cl.k > 1 || !g.per[2]) ? c - g.sxy : c + (long)(g.nz - 1) * g.sxy;
+  for_cells(g, zr, [&](int ci, int cj, int ck, long c) {
+    const long cw = (ci > 1 || !g.per[0]) ? c - 1 : c + (g.nx - 1);
+    const long cs = (cj > 1 || !g.per[1]) ? c - g.sx : c + (long)(g.ny - 1) * g.sx;
+    const long cb = (ck > 1 || !g.per[2]) ? c - g.sxy : c + (long)(g.nz - 1) * g.sxy;
     const double d = ((double)F[c] - (double)F[cw]) * g.idx + ((double)G[c] - (double)G[cs]) * g.idy +
                      ((double)H[c] - (double)H[cb]) * g.idz;
     const T r = T(d * idt);
     rhs[c] = r;
     acc += (double)r * (double)r;
-  }
+  });
+  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned nbk = gridDim.x * gridDim.y * gridDim.z;
   double s = block_sum(acc, sh);
-  if (publish_partial(part, blockIdx.x, s, ctl, gridDim.x, &sh_last)) {
-    double tot = sum_partials(part, gridDim.x, sh);
-    if (threadIdx.x == 0) {
+  if (publish_partial(part, bid, s, ctl, nbk, &sh_last)) {
+    double tot = sum_partials(part, nbk, sh);
+    if (flat_tid() == 0) {
       const double rms = sqrt(tot / (double)n);
       ctl->rhs_rms = rms;
       ctl->thr = tol * (rms > 1e-300 ? rms : 1e-300);
@@ -295,49 +277,45 @@ k_rhs(const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
 // of each component; p ghosts hold periodic images where needed.
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_project(const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
+k_project(int zr, const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
           const double* __restrict__ p, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w,
           Geo g, const Ctl* __restrict__ ctl, int unit_dt) {
   const double dt = unit_dt ? 1.0 : ctl->dt;
-  const long n = (long)g.nx * g.ny * g.nz;
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    const Cell cl = cell_of(g, t);
-    const long c = cl.c;
+  for_cells(g, zr, [&](int ci, int cj, int ck, long c) {
     const double pc = p[c];
-    if (cl.i <= g.hi[0]) u[c] = T((double)F[c] - dt * (p[c + 1] - pc) * g.idx);
-    if (cl.j <= g.hi[1]) v[c] = T((double)G[c] - dt * (p[c + g.sx] - pc) * g.idy);
-    if (cl.k <= g.hi[2]) w[c] = T((double)H[c] - dt * (p[c + g.sxy] - pc) * g.idz);
-  }
+    if (ci <= g.hi[0]) u[c] = T((double)F[c] - dt * (p[c + 1] - pc) * g.idx);
+    if (cj <= g.hi[1]) v[c] = T((double)G[c] - dt * (p[c + g.sx] - pc) * g.idy);
+    if (ck <= g.hi[2]) w[c] = T((double)H[c] - dt * (p[c + g.sxy] - pc) * g.idz);
+  });
 }
 
 // Adaptive step: tau * min(diffusive limit, h_d / max|u_d|) with the maxima
 // over the unknowns and the wall speeds.
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_umax(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w, Geo g, Ctl* ctl,
+k_umax(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w, Geo g, Ctl* ctl,
        double* part, double re, double tau, double wu, double wv, double ww) {
   __shared__ double sh[16];
   __shared__ int sh_last;
-  const long n = (long)g.nx * g.ny * g.nz;
   double m[3] = {0.0, 0.0, 0.0};
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    const Cell cl = cell_of(g, t);
-    if (cl.i <= g.hi[0]) m[0] = fmax(m[0], fabs((double)u[cl.c]));
-    if (cl.j <= g.hi[1]) m[1] = fmax(m[1], fabs((double)v[cl.c]));
-    if (cl.k <= g.hi[2]) m[2] = fmax(m[2], fabs((double)w[cl.c]));
-  }
+  for_cells(g, zr, [&](int ci, int cj, int ck, long c) {
+    if (ci <= g.hi[0]) m[0] = fmax(m[0], fabs((double)u[c]));
+    if (cj <= g.hi[1]) m[1] = fmax(m[1], fabs((double)v[c]));
+    if (ck <= g.hi[2]) m[2] = fmax(m[2], fabs((double)w[c]));
+  });
   double r[3];
   for (int d = 0; d < 3; d++) r[d] = block_max(m[d], sh);
-  const unsigned nb = gridDim.x;
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = r[0];
-    part[nb + blockIdx.x] = r[1];
-    part[2 * nb + blockIdx.x] = r[2];
+  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+  if (flat_tid() == 0) {
+    part[bid] = r[0];
+    part[nb + bid] = r[1];
+    part[2 * nb + bid] = r[2];
   }
-  if (publish_partial(part + 3 * nb, blockIdx.x, 0.0, ctl, nb, &sh_last)) {
+  if (publish_partial(part + 3 * nb, bid, 0.0, ctl, nb, &sh_last)) {
     double mm[3];
     for (int d = 0; d < 3; d++) mm[d] = max_partials(part + d * nb, nb, sh);
-    if (threadIdx.x == 0) {
+    if (flat_tid() == 0) {
       const double wall[3] = {wu, wv, ww};
       const double h[3] = {g.dx, g.dy, g.dz};
       double lim = (re / 2.0) / (g.idx2 + g.idy2 + g.idz2);
@@ -354,15 +332,12 @@ k_umax(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w
 
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_divergence(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
+k_divergence(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
              T* __restrict__ out, Geo g) {
-  const long n = (long)g.nx * g.ny * g.nz;
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    const Cell cl = cell_of(g, t);
-    const long c = cl.c;
+  for_cells(g, zr, [&](int, int, int, long c) {
     out[c] = T(((double)u[c] - (double)u[c - 1]) * g.idx + ((double)v[c] - (double)v[c - g.sx]) * g.idy +
                ((double)w[c] - (double)w[c - g.sxy]) * g.idz);
-  }
+  });
 }
 
 __global__ void k_mask(double* __restrict__ q, Geo g, int comp) {
@@ -419,8 +394,7 @@ template <class T>
 hipError_t launch_fgh(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, const T* fx,
                       const T* fy, const T* fz, T* F, T* G, T* H, const Ctl* ctl, double re,
                       double gamma, const double gf[3]) {
-  long n = (long)g.nx * g.ny * g.nz;
-  k_fgh<T><<<grid_for(n, 1 << 16), kBlock, 0, st>>>(u, v, w, fx, fy, fz, F, G, H, g, ctl, 1.0 / re,
+  k_fgh<T><<<cell_grid(g, false), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, false), u, v, w, fx, fy, fz, F, G, H, g, ctl, 1.0 / re,
                                                      gamma, gf[0], gf[1], gf[2]);
   return hipGetLastError();
 }
@@ -428,43 +402,41 @@ hipError_t launch_fgh(hipStream_t st, const Geo& g, const T* u, const T* v, cons
 size_t reduce_blocks(const Geo& g) {
   long n = (long)g.nx * g.ny * g.nz;
   size_t m = (size_t)grid_for(n);
+  if ((size_t)cell_blocks(g, true) > m) m = cell_blocks(g, true);
   // the fused sweep has the most workgroups with 4 rows and 1-plane chunks
   const size_t f = (size_t)fused_num_blocks(g, SorShape{4, 1});
   if (f > m) m = f;
+  if ((size_t)pass_max_partials(g) > m) m = pass_max_partials(g);
   return 4 * m + 64;
 }
 
 template <class T>
 hipError_t launch_rhs(hipStream_t st, const Geo& g, const T* F, const T* G, const T* H, T* rhs,
                       Ctl* ctl, double* part, double tol, double unit_dt) {
-  long n = (long)g.nx * g.ny * g.nz;
-  k_rhs<T><<<grid_for(n), kBlock, 0, st>>>(F, G, H, rhs, g, ctl, part, tol, unit_dt != 0.0);
+  k_rhs<T><<<cell_grid(g, true), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, true), F, G, H, rhs, g, ctl, part, tol, unit_dt != 0.0);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_project(hipStream_t st, const Geo& g, const T* F, const T* G, const T* H,
                           const double* p, T* u, T* v, T* w, const Ctl* ctl, double unit_dt) {
-  long n = (long)g.nx * g.ny * g.nz;
-  k_project<T><<<grid_for(n, 1 << 16), kBlock, 0, st>>>(F, G, H, p, u, v, w, g, ctl, unit_dt != 0.0);
+  k_project<T><<<cell_grid(g, false), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, false), F, G, H, p, u, v, w, g, ctl, unit_dt != 0.0);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_umax(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, Ctl* ctl,
                        double* part, double re, double tau, const double wall[6][3]) {
-  long n = (long)g.nx * g.ny * g.nz;
   double wm[3] = {0, 0, 0};
   for (int f = 0; f < 6; f++)
     for (int c = 0; c < 3; c++) wm[c] = fmax(wm[c], fabs(wall[f][c]));
-  k_umax<T><<<grid_for(n), kBlock, 0, st>>>(u, v, w, g, ctl, part, re, tau, wm[0], wm[1], wm[2]);
+  k_umax<T><<<cell_grid(g, true), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, true), u, v, w, g, ctl, part, re, tau, wm[0], wm[1], wm[2]);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_divergence(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, T* out) {
-  long n = (long)g.nx * g.ny * g.nz;
-  k_divergence<T><<<grid_for(n, 1 << 16), kBlock, 0, st>>>(u, v, w, out, g);
+  k_divergence<T><<<cell_grid(g, false), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, false), u, v, w, out, g);
   return hipGetLastError();
 }
 

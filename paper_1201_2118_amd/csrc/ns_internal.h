@@ -41,13 +41,16 @@ struct Ctl {
 };
 
 // Tunables of the red-black sweep (chosen per grid by the autotuner).
-// ty > 0: fused single-pass kernel with ty interior rows per workgroup (the
-// x width is fixed at 60 = 64 - 4 halo) and zc planes per z chunk (0 =
-// whole column); ty < 0: unfused reference kernels (one pass per colour).
+// ty = 4 / 8 / 12: fused one-sweep kernel with ty interior rows per
+// workgroup (the x width is fixed at 60 = 64 - 4 halo); ty = 16 / 24 / 32:
+// pass kernel, two sweeps per launch, ty rows per workgroup including the
+// 4-cell halo on each side; zc planes per z chunk (0 = whole column).
+// ty < 0: unfused reference kernels (one pass per colour).
 struct SorShape {
   int ty;
   int zc;
 };
+inline bool shape_is_pass(const SorShape& s) { return s.ty >= 16; }
 
 // ---- kernel launchers (kernels.hip / sor.hip / adjoint.hip) ----
 // All launchers enqueue on `st` and return the hipGetLastError() status.
@@ -86,6 +89,50 @@ hipError_t launch_defect(hipStream_t st, const Geo& g, const double* p_in, const
                          double eta);
 
 size_t reduce_blocks(const Geo& g);  // partial-sum slots any reduction may need
+
+// Cell kernels run 64 x 4 threads per workgroup over (x, y); the
+// workgroups of one (x, y) tile split z into runs of consecutive planes.
+// Consecutive lanes take consecutive x, so a wave reads 64 contiguous values
+// per row.  Kernels without a reduction take short runs (many workgroups);
+// kernels with one take runs long enough to keep the partial sums that the
+// last workgroup adds up to a few thousand.
+#ifndef NS_CELL_Z
+#define NS_CELL_Z 4  // planes per workgroup, kernels without a reduction
+#endif
+constexpr int kCellX = 64, kCellY = 4;
+constexpr long kCellRedBlocks = 4096;  // target workgroups of a reducing cell kernel
+inline int cell_zrun(const Geo& g, bool reducing) {
+  const long cols = (long)((g.nx + kCellX - 1) / kCellX) * ((g.ny + kCellY - 1) / kCellY);
+  long z = NS_CELL_Z;
+  if (reducing) {
+    const long want = (cols * g.nz + kCellRedBlocks - 1) / kCellRedBlocks;
+    if (want > z) z = want;
+  }
+  const long minz = (g.nz + 65534) / 65535;  // grid z limit
+  if (z < minz) z = minz;
+  return (int)(z < g.nz ? z : g.nz);
+}
+inline dim3 cell_grid(const Geo& g, bool reducing) {
+  const int bx = (g.nx + kCellX - 1) / kCellX, by = (g.ny + kCellY - 1) / kCellY;
+  const int zr = cell_zrun(g, reducing);
+  return dim3(bx, by, (g.nz + zr - 1) / zr);
+}
+// f(i, j, k, c) for every interior cell of this workgroup's (x, y) tile and
+// run of zr planes.
+template <class F>
+__device__ __forceinline__ void for_cells(const Geo& g, int zr, F&& f) {
+  const int i = blockIdx.x * kCellX + threadIdx.x + 1;
+  const int j = blockIdx.y * kCellY + threadIdx.y + 1;
+  if (i > g.nx || j > g.ny) return;
+  const int k0 = blockIdx.z * zr + 1;
+  const int k1 = min(g.nz, k0 + zr - 1);
+  long c = (long)k0 * g.sxy + (long)j * g.sx + i;
+  for (int k = k0; k <= k1; k++, c += g.sxy) f(i, j, k, c);
+}
+inline unsigned cell_blocks(const Geo& g, bool reducing) {
+  const dim3 d = cell_grid(g, reducing);
+  return d.x * d.y * d.z;
+}
 int sor_num_blocks(const Geo& g, const SorShape& s);
 // Fused sweep (one pass): shape.ty rows per workgroup in {4, 8, 12},
 // shape.zc planes per z chunk (0 = whole column).
@@ -94,6 +141,18 @@ template <class T> hipError_t launch_sor_fused(hipStream_t st, const Geo& g, con
                                               int sweep_idx, int itermax, int write, int zero_in,
                                               int thr_is_inner, const SorShape& shape);
 int fused_num_blocks(const Geo& g, const SorShape& s);
+// Pass kernel (sor_pass.hip): ns = 1 or 2 sweeps per launch, first sweep
+// index m (input iterate m - 1).  part == nullptr forces the sweep whatever
+// the done flag says and skips the residual and stop rule.
+template <class T> hipError_t launch_sor_pass(hipStream_t st, const Geo& g, const T* p_in, T* p_out,
+                                             const T* rhs, Ctl* ctl, double* part, double omega, int m,
+                                             int itermax, int write, int zero_in, int inner, int ns,
+                                             const SorShape& shape);
+bool pass_shape_ok(const SorShape& s);
+bool pass_grid_ok(const Geo& g, size_t esz);  // periodic axes >= 4 cells, plane offsets in 31 bits
+int pass_max_partials(const Geo& g);
+int pass_resident_groups(int ty, bool f32, int ns);
+int pass_columns(const Geo& g, int ty, int ns);
 bool fused_shape_ok(const SorShape& s);
 int fused_resident(int ty, bool f32);       // workgroups resident on the device at once
 int fused_columns(const Geo& g, int ty);    // x-y tiles of one z chunk

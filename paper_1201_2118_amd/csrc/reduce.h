@@ -66,9 +66,18 @@ __device__ __forceinline__ bool publish_partial(double* part, int slot, double v
 // Deterministic sum of n partials by one workgroup (fixed strided order,
 // then block_sum); valid in thread 0.
 __device__ __forceinline__ double sum_partials(const double* part, unsigned n, double* sh) {
-  double s = 0.0;
-  for (unsigned i = flat_tid(); i < n; i += flat_size()) s += part[i];
-  return block_sum(s, sh);
+  // four independent loads in flight per thread, then a fixed combination
+  const unsigned t = flat_tid(), w = flat_size();
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  unsigned i = t;
+  for (; i + 3 * w < n; i += 4 * w) {
+    s0 += part[i];
+    s1 += part[i + w];
+    s2 += part[i + 2 * w];
+    s3 += part[i + 3 * w];
+  }
+  for (; i < n; i += w) s0 += part[i];
+  return block_sum((s0 + s1) + (s2 + s3), sh);
 }
 
 __device__ __forceinline__ double max_partials(const double* part, unsigned n, double* sh) {

@@ -189,9 +189,15 @@ ns_status validate(const ns_params& p, int idx) {
   for (int c = 0; c < 3; c++)
     if (!std::isfinite(p.g[c])) return bad("body force must be finite");
   if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING)) return bad("unknown flag bits");
-  if (!(p.tile[0] == -1 || p.tile[0] == 0 || p.tile[0] == 4 || p.tile[0] == 8 || p.tile[0] == 12))
-    return bad("tile[0] must be -1, 0, 4, 8 or 12");
+  if (!(p.tile[0] == -1 || p.tile[0] == 0 || p.tile[0] == 4 || p.tile[0] == 8 || p.tile[0] == 12 ||
+        p.tile[0] == 16 || p.tile[0] == 24 || p.tile[0] == 32))
+    return bad("tile[0] must be -1, 0, 4, 8, 12, 16, 24 or 32");
   if (p.tile[1] < 0) return bad("tile[1] must be >= 0");
+  if (p.tile[0] > 0 && (double)(p.nx + 2) * (p.ny + 2) * (p.precision == NS_MIXED ? 4 : 8) >= 2147483648.0)
+    return bad("planes this large need the unfused sweeps (tile = {-1, 0})");
+  if (p.tile[0] >= 16)
+    for (int a = 0; a < 3; a++)
+      if (p.bc[a] == NS_BC_PERIODIC && n[a] < 4) return bad("the two-sweep pass needs periodic axes of at least 4 cells");
   if (p.dt > 0 && !(p.flags & NS_ALLOW_UNSTABLE)) {
     const double dx = p.lx / p.nx, dy = p.ly / p.ny, dz = p.lz / p.nz;
     const double diff = p.dt / p.re * (1 / (dx * dx) + 1 / (dy * dy) + 1 / (dz * dz));
@@ -212,9 +218,11 @@ ns_status validate(const ns_params& p, int idx) {
 
 // Sweep shape: the caller's tile descriptor, or a size-based default that
 // the autotuner may replace (see autotune()).
-SorShape pick_shape(const ns_params& p, const Geo& g) {
+SorShape pick_shape(const ns_params& p, const Geo& g, size_t esz) {
   if (p.tile[0] < 0) return SorShape{-1, 0};
   if (p.tile[0] > 0) return SorShape{p.tile[0], p.tile[1]};
+  // the fused kernels address a plane with 32-bit byte offsets
+  if ((double)g.sxy * (double)esz >= 2147483648.0) return SorShape{-1, 0};
   const long n = (long)g.nx * g.ny * g.nz;
   if (n >= (1L << 24)) return SorShape{8, 128};
   return SorShape{8, 0};
@@ -251,9 +259,12 @@ ns_status tune_run(ns_solver* s, Inst& I, Ctl* tctl, const SorShape& sh, float* 
   hipError_t e = hipSuccess;
   for (int it = 0; it < 4 && e == hipSuccess; it++) {
     if (it == 1) e = hipEventRecord(a, s->stream);
-    // sweep index 1: the residual of iterate 0 is never a stop decision
-    if (e == hipSuccess) e = launch_sor_sweep<T>(s->stream, I.g, in, out, rhs, tctl, I.part, I.prm.omega, 1, 1 << 30,
-                                                1, 0, 0, sh);
+    // sweep index 1 (pass: 0): no residual of these launches is a stop decision
+    if (e == hipSuccess)
+      e = shape_is_pass(sh) ? launch_sor_pass<T>(s->stream, I.g, in, out, rhs, tctl, I.part, I.prm.omega, 0,
+                                                 1 << 30, 1, 0, 0, 2, sh)
+                            : launch_sor_sweep<T>(s->stream, I.g, in, out, rhs, tctl, I.part, I.prm.omega, 1,
+                                                  1 << 30, 1, 0, 0, sh);
   }
   if (e == hipSuccess) e = hipEventRecord(b, s->stream);
   if (e == hipSuccess) e = hipEventSynchronize(b);
@@ -261,6 +272,7 @@ ns_status tune_run(ns_solver* s, Inst& I, Ctl* tctl, const SorShape& sh, float* 
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (e != hipSuccess) return fail_hip(s, "autotune", e);
+  if (shape_is_pass(sh)) *ms *= 0.5f;  // per sweep
   return NS_OK;
 }
 
@@ -275,14 +287,17 @@ ns_status autotune(ns_solver* s, Inst& I) {
   }
   Ctl* tctl = nullptr;
   HCK(s, dmalloc((void**)&tctl, sizeof(Ctl)));
-  const int rows[3] = {4, 8, 12};
+  const bool pass_ok = pass_grid_ok(I.g, I.esz);
+  const int rows[6] = {4, 8, 12, 16, 24, 32};
   float best = 1e30f;
   SorShape pick = I.shape;
   ns_status st = NS_OK;
-  for (int r = 0; r < 3 && st == NS_OK; r++) {
+  for (int r = 0; r < 6 && st == NS_OK; r++) {
+    const bool pass = rows[r] >= 16;
+    if (pass && !pass_ok) continue;
     std::vector<int> zcs = {0, 32, 64, 128};
-    const int res = fused_resident(rows[r], I.mixed);
-    const int cols = fused_columns(I.g, rows[r]);
+    const int res = pass ? pass_resident_groups(rows[r], I.mixed, 2) : fused_resident(rows[r], I.mixed);
+    const int cols = pass ? pass_columns(I.g, rows[r], 2) : fused_columns(I.g, rows[r]);
     for (int k = 1; k <= 8 && res > 0; k++) {
       const int ntz = (int)((long)k * res / cols);
       if (ntz < 1) continue;
@@ -463,29 +478,78 @@ ns_status poll(ns_solver* s, int idx) {
 // ---- Poisson solves ----------------------------------------------------------
 // FP64 red-black SOR on A p = rhs from P[*cur]; on return *cur indexes the
 // accepted iterate, *sweeps its sweep count.
+// One launch of a solve: ns sweeps (2 only with a pass shape) from the
+// iterate in p_in into p_out, first sweep index m; ns = 0 computes only the
+// residual of p_in.  force: sweep whatever the done flag says, no residual.
+template <class T>
+hipError_t sweep_launch(ns_solver* s, Inst& I, const T* p_in, T* p_out, const T* rhs, int m, int itermax,
+                        int zero_in, int inner, int ns, bool force = false) {
+  const int write = ns > 0;
+  if (shape_is_pass(I.shape))
+    return launch_sor_pass<T>(s->stream, I.g, p_in, p_out, rhs, I.ctl, force ? nullptr : I.part, I.prm.omega, m,
+                              itermax, write, zero_in, inner, ns > 0 ? ns : 1, I.shape);
+  if (force || ns > 1) return hipErrorInvalidValue;
+  return launch_sor_sweep<T>(s->stream, I.g, p_in, p_out, rhs, I.ctl, I.part, I.prm.omega, m, itermax, write,
+                             zero_in, inner, I.shape);
+}
+
+// Launches of one solve, to find the buffer of the accepted iterate.
+struct SweepLaunch {
+  int m1, ns, in, out;  // first sweep index, sweeps, input / output buffer
+};
+
+// Buffer holding iterate f, or -1.  An iterate that a two-sweep pass held
+// only in registers is swept again (forced, bitwise the same arithmetic)
+// from the pass's input into its output buffer.
+template <class T>
+int locate_iterate(ns_solver* s, Inst& I, const std::vector<SweepLaunch>& L, T* const buf[2], const T* rhs, int f,
+                   int inner, int tag, long long bytes, ns_status* st) {
+  *st = NS_OK;
+  for (const SweepLaunch& l : L) {
+    if (l.m1 - 1 == f) return l.in;
+    if (l.ns == 2 && l.m1 == f) {
+      Timed t(s, NS_T_SOR, tag, bytes);
+      const hipError_t e =
+          sweep_launch<T>(s, I, buf[l.in], buf[l.out], rhs, f, 1 << 30, l.m1 == 1 && inner, inner, 1, true);
+      if (e != hipSuccess) {
+        *st = fail_hip(s, "sweep", e);
+        return -1;
+      }
+      return l.out;
+    }
+  }
+  return -1;
+}
+
+// FP64 red-black SOR on A p = rhs from P[*cur]; on return *cur indexes the
+// accepted iterate, *sweeps its sweep count.
 ns_status solve_fp64(ns_solver* s, int idx, double* P[2], int* cur, int* sweeps) {
   Inst& I = s->in[idx];
   const int itermax = I.prm.itermax;
   const long N = (long)I.g.nx * I.g.ny * I.g.nz;
-  int m = 0;
+  const bool pairs = shape_is_pass(I.shape);
+  int m = 0;     // newest iterate launched
+  int b = *cur;  // its buffer
+  std::vector<SweepLaunch> L;
   int pred = std::min(std::max(I.pred + 2, 4), itermax + 1);
   bool first = true;
   for (;;) {
     int chunk = first ? pred : std::max(4, pred / 4);
     first = false;
     bool last_pass = false;
-    for (int c = 0; c < chunk; c++) {
-      m++;
-      if (m <= itermax) {
-        Timed t(s, NS_T_SOR, m, 24LL * N);
-        HCK(s, launch_sor_sweep<double>(s->stream, I.g, P[(*cur + m - 1) & 1], P[(*cur + m) & 1],
-                                        (const double*)I.rhs, I.ctl, I.part, I.prm.omega, m, itermax, 1,
-                                        0, 0, I.shape));
+    for (int c = 0; c < chunk;) {
+      if (m < itermax) {
+        const int ns = pairs && m + 2 <= itermax ? 2 : 1;
+        Timed t(s, NS_T_SOR, m + 1, 24LL * N);
+        HCK(s, sweep_launch<double>(s, I, P[b], P[b ^ 1], (const double*)I.rhs, m + 1, itermax, 0, 0, ns));
+        L.push_back({m + 1, ns, b, b ^ 1});
+        b ^= 1;
+        m += ns;
+        c += ns;
       } else {
-        Timed t(s, NS_T_SOR, m, 16LL * N);
-        HCK(s, launch_sor_sweep<double>(s->stream, I.g, P[(*cur + itermax) & 1], nullptr,
-                                        (const double*)I.rhs, I.ctl, I.part, I.prm.omega, m, itermax, 0,
-                                        0, 0, I.shape));
+        Timed t(s, NS_T_SOR, m + 1, 16LL * N);
+        HCK(s, sweep_launch<double>(s, I, P[b], (double*)nullptr, (const double*)I.rhs, m + 1, itermax, 0, 0, 0));
+        L.push_back({m + 1, 0, b, -1});
         last_pass = true;
         break;
       }
@@ -496,8 +560,12 @@ ns_status solve_fp64(ns_solver* s, int idx, double* P[2], int* cur, int* sweeps)
   }
   const Ctl& h = s->hctl[idx];
   if (!h.done) return fail(s, NS_E_DEVICE, "Poisson solve ended without a decision");
+  ns_status st = NS_OK;
+  const int fb = locate_iterate<double>(s, I, L, P, (const double*)I.rhs, h.final_, 0, h.final_, 24LL * N, &st);
+  if (st != NS_OK) return st;
+  if (fb < 0) return fail(s, NS_E_DEVICE, "accepted iterate not found");
   *sweeps = h.final_;
-  *cur = (*cur + h.final_) & 1;
+  *cur = fb;
   I.pred = h.final_;
   return NS_OK;
 }
@@ -509,6 +577,7 @@ ns_status solve_mixed(ns_solver* s, int idx, int* sweeps, int* outer) {
   State& S = I.s;
   const int itermax = I.prm.itermax;
   const long N = (long)I.g.nx * I.g.ny * I.g.nz;
+  const bool pairs = shape_is_pass(I.shape);
   int used = 0;
   *outer = 0;
   {
@@ -524,23 +593,35 @@ ns_status solve_mixed(ns_solver* s, int idx, int* sweeps, int* outer) {
     (*outer)++;
     const int budget = itermax - used;
     int m = 0;
+    int b = 0;  // buffer of iterate m (iterate 0 is zero and never read)
+    std::vector<SweepLaunch> L;
     int pred = std::min(std::max(I.pred + 2, 4), budget);
     bool first = true;
-    int f = -1;
+    int f = -1, fb = -1;
     const size_t rec0 = s->recs.size();
     for (;;) {
       int chunk = first ? pred : std::max(4, pred / 4);
       first = false;
-      for (int c = 0; c < chunk && m < budget; c++) {
-        m++;
-        Timed t(s, NS_T_SOR, 1000000 + m, (m == 1 ? 8LL : 12LL) * N);
-        HCK(s, launch_sor_sweep<float>(s->stream, I.g, I.e[(m - 1) & 1], I.e[m & 1], I.r, I.ctl, I.part,
-                                       I.prm.omega, m, itermax + 1, 1, m == 1, 1, I.shape));
+      for (int c = 0; c < chunk && m < budget;) {
+        const int ns = pairs && m + 2 <= budget ? 2 : 1;
+        Timed t(s, NS_T_SOR, 1000000 + m + 1, (m == 0 ? 8LL : 12LL) * N);
+        HCK(s, sweep_launch<float>(s, I, I.e[b], I.e[b ^ 1], I.r, m + 1, itermax + 1, m == 0, 1, ns));
+        L.push_back({m + 1, ns, b, b ^ 1});
+        b ^= 1;
+        m += ns;
+        c += ns;
       }
       e = poll(s, idx);
       if (e != NS_OK) return e;
-      if (s->hctl[idx].done) { f = s->hctl[idx].final_; break; }
-      if (m >= budget) { f = budget; break; }
+      if (s->hctl[idx].done) {
+        f = s->hctl[idx].final_;
+        ns_status st = NS_OK;
+        fb = locate_iterate<float>(s, I, L, I.e, I.r, f, 1, 1000000 + f, 12LL * N, &st);
+        if (st != NS_OK) return st;
+        if (fb < 0) return fail(s, NS_E_DEVICE, "accepted correction not found");
+        break;
+      }
+      if (m >= budget) { f = budget; fb = b; break; }
     }
     used += f;
     I.pred = f;
@@ -548,7 +629,7 @@ ns_status solve_mixed(ns_solver* s, int idx, int* sweeps, int* outer) {
     for (size_t q = rec0; q < s->recs.size(); q++)
       if (s->recs[q].stage == NS_T_SOR && s->recs[q].m - 1000000 > f + 1) s->recs[q].stage = NS_T_COUNT - 1;
     Timed t(s, NS_T_DEFECT, 0, 40LL * N);
-    HCK(s, launch_defect(s->stream, I.g, S.p[S.pcur], I.e[f & 1], S.p[S.pcur ^ 1], (const float*)I.rhs, I.r,
+    HCK(s, launch_defect(s->stream, I.g, S.p[S.pcur], I.e[fb], S.p[S.pcur ^ 1], (const float*)I.rhs, I.r,
                          I.ctl, I.part, I.prm.eta));
     S.pcur ^= 1;
   }
@@ -927,7 +1008,7 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
     if (hipMemcpy(I.ctl, &c, sizeof c, hipMemcpyHostToDevice) != hipSuccess)
       return bail(NS_E_DEVICE, "control block upload failed");
     I.rec_valid = I.prm.checkpoint_every > 0;
-    I.shape = pick_shape(I.prm, I.g);
+    I.shape = pick_shape(I.prm, I.g, I.esz);
   }
   // staging buffer for FP32 conversions of host data
   bool any_mixed = false;
@@ -949,7 +1030,7 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
   // several instances of one precision: one launch per sweep for all of them
   {
     bool same = n_instances > 1;
-    for (auto& I : s->in) same &= I.mixed == s->in[0].mixed && I.prm.tile[0] >= 0;
+    for (auto& I : s->in) same &= I.mixed == s->in[0].mixed && I.prm.tile[0] >= 0 && I.prm.tile[0] <= 12;
     s->batched = same;
   }
   if (s->batched) {

@@ -145,17 +145,15 @@ k_sor_black(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
 // arithmetic, stored as FP32), RMS of the FP64 r into ctl->res; decides
 // outer convergence and sets the inner threshold eta * RMS(r).
 __global__ void __launch_bounds__(kBlock)
-k_defect(const double* __restrict__ p_in, const float* __restrict__ e, double* __restrict__ p_out,
+k_defect(int zr, const double* __restrict__ p_in, const float* __restrict__ e, double* __restrict__ p_out,
          const float* __restrict__ rhs, float* __restrict__ r, Geo g, Ctl* ctl, double* part,
          double eta) {
   __shared__ double sh[16];
   __shared__ int sh_last;
   const long n = (long)g.nx * g.ny * g.nz;
   double acc = 0.0;
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    const Cell cl = cell_of(g, t);
-    const Nb nb = neighbours(g, cl.i, cl.j, cl.k);
-    const long c = cl.c;
+  for_cells(g, zr, [&](int ci, int cj, int ck, long c) {
+    const Nb nb = neighbours(g, ci, cj, ck);
     const double pc = p_in[c] + (e ? (double)e[c] : 0.0);
     double s = 0.0;
 #pragma unroll
@@ -167,11 +165,13 @@ k_defect(const double* __restrict__ p_in, const float* __restrict__ e, double* _
     r[c] = (float)rr;
     acc += rr * rr;
     if (e) p_out[c] = pc;
-  }
+  });
+  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned nbk = gridDim.x * gridDim.y * gridDim.z;
   double s = block_sum(acc, sh);
-  if (publish_partial(part, blockIdx.x, s, ctl, gridDim.x, &sh_last)) {
-    double tot = sum_partials(part, gridDim.x, sh);
-    if (threadIdx.x == 0) {
+  if (publish_partial(part, bid, s, ctl, nbk, &sh_last)) {
+    double tot = sum_partials(part, nbk, sh);
+    if (flat_tid() == 0) {
       // an identically zero rhs needs no correction at all
       const double res = ctl->rhs_rms == 0.0 ? 0.0 : sqrt(tot / (double)n);
       const bool fin = isfinite(res);
@@ -213,7 +213,7 @@ hipError_t launch_defect(hipStream_t st, const Geo& g, const double* p_in, const
                          double* p_out, const float* rhs, float* r, Ctl* ctl, double* part,
                          double eta) {
   const long n = (long)g.nx * g.ny * g.nz;
-  k_defect<<<grid_for(n), kBlock, 0, st>>>(p_in, e, p_out, rhs, r, g, ctl, part, eta);
+  k_defect<<<cell_grid(g, true), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, true), p_in, e, p_out, rhs, r, g, ctl, part, eta);
   return hipGetLastError();
 }
 

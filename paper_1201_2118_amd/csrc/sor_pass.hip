@@ -1,0 +1,570 @@
+// sor_pass.hip -- NS (1 or 2) red-black SOR sweeps in one pass over HBM.
+//
+// Temporal blocking of the red-black iteration: a workgroup reads its tile of
+// the input iterate and of the rhs once and carries it through NS complete
+// sweeps (red then black, repeated) before writing the last iterate, so a
+// pass of two sweeps costs the HBM traffic of one.  Each sweep is exactly
+// the sweep of the unfused kernels (the same per-cell update in the same
+// colour order); the residual of every input iterate is accumulated on the
+// way, so the stop rule is applied after every sweep as before.
+//
+// Workgroup: 8 waves stacked in y; wave w owns R consecutive rows of the
+// tile (rows w R .. w R + R - 1) and each lane one x position, so a lane
+// keeps R cells of a plane in registers.  x neighbours come from the
+// adjacent lanes through DPP wave shifts, y neighbours inside a wave's rows
+// from its own registers, and across waves from one LDS row per wave edge.
+// The tile is marched through z; with plane L the newest loaded, one step
+// computes
+//   A: residual of the input and red update at plane L - 1,
+//   B: black update at plane L - 2 (first sweep's iterate),
+// and for NS = 2 additionally
+//   C: residual of that iterate and its red update at plane L - 3,
+//   D: black update at plane L - 4 (second sweep's iterate),
+// then writes the last stage's plane.  Each stage consumes its own plane
+// and the planes on either side from registers; a value that crosses a
+// wave edge goes through LDS with one barrier per step.  The halo is
+// 2 NS cells in x, y and z and is recomputed redundantly, so no workgroup
+// reads what another writes; input and output are different buffers.
+//
+// The residual r = sum_nb a_nb p_nb - a_c p_c - rhs is evaluated with an
+// explicit fused multiply-add chain (one rounding sequence for every
+// instantiation), and a cell's update is p + (omega / a_c) r.  Across a
+// wall the coefficient is zero and positions outside the domain load a
+// clamped cell (finite); periodic axes load the periodic image.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <type_traits>
+
+#include "ns_internal.h"
+#include "reduce.h"
+
+namespace ns {
+
+namespace {
+
+constexpr int kLanes = 64;  // x positions per row (one wave)
+constexpr int kWaves = 8;   // waves per workgroup, stacked in y
+
+__device__ __forceinline__ int dpp_left(int v) {  // lane l receives lane l - 1 (0 at lane 0)
+  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
+}
+__device__ __forceinline__ int dpp_right(int v) {  // lane l receives lane l + 1 (0 at lane 63)
+  return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);
+}
+__device__ __forceinline__ float from_left(float v) {
+  return __builtin_bit_cast(float, dpp_left(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __builtin_bit_cast(float, dpp_right(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const unsigned lo = (unsigned)dpp_left((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_left((int)(unsigned)(b >> 32));
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double from_right(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const unsigned lo = (unsigned)dpp_right((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_right((int)(unsigned)(b >> 32));
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Index of the cell a virtual position loads: the periodic image (one wrap;
+// the axis is at least as long as the halo), clamped to the domain.
+__device__ __forceinline__ int wrap_clamp(int i, int n, int per) {
+  if (per) i += (i < 1 ? n : 0) - (i > n ? n : 0);
+  return i < 1 ? 1 : (i > n ? n : i);
+}
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// sum_nb a_nb p_nb - diag p_c, one rounding sequence.
+template <class T>
+__device__ __forceinline__ T stencil(T pc, T pw, T pe, T ps, T pn, T pd, T pu, T axm, T axp, T aym, T ayp,
+                                     T azm, T azp, T diag) {
+  T t = axm * pw;
+  t = fmaT(axp, pe, t);
+  t = fmaT(aym, ps, t);
+  t = fmaT(ayp, pn, t);
+  t = fmaT(azm, pd, t);
+  t = fmaT(azp, pu, t);
+  return fmaT(-diag, pc, t);
+}
+
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <class T>
+__device__ __forceinline__ T ld_at(const T* base, unsigned off) {
+  return *(const T*)((const char*)base + off);
+}
+template <class T>
+__device__ __forceinline__ void st_at(T* base, unsigned off, T v) {
+  *(T*)((char*)base + off) = v;
+}
+
+// LDS edge rows: per quantity and step parity, two rows (top, bottom) per
+// wave.
+constexpr int kEdge = kWaves * 2 * kLanes;
+
+template <class T, int NS, int R, bool ZIN>
+__device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restrict__ p_out,
+                                          const T* __restrict__ rhs, const Geo& g, double omega, int write,
+                                          int tile, int zc, int ntx, int nty, T* __restrict__ E, double& acc1,
+                                          double& acc2) {
+  constexpr int H = 2 * NS;
+  constexpr int TX = kLanes - 2 * H;
+  constexpr int ROWS = R * kWaves;
+  constexpr int TY = ROWS - 2 * H;
+  const int tx = threadIdx.x;
+  const int wy = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+  const int bx = tile % ntx;
+  const int rest = tile / ntx;
+  const int by = rest % nty;
+  const int bz = rest / nty;
+  const int i = bx * TX + tx - (H - 1);
+  const int j0 = by * TY + wy * R - (H - 1);  // row 0 of this wave (uniform)
+  const int z0 = 1 + bz * zc;
+  const int z1 = min(g.nz, z0 + zc - 1);
+  const int per0 = g.per[0], per1 = g.per[1], per2 = g.per[2];
+
+  const bool ownx = tx >= H && tx < kLanes - H && i <= g.nx;
+  const bool xlo = i > 1 || per0, xhi = i < g.nx || per0;
+  const T axm = xlo ? T(g.idx2) : T(0);
+  const T axp = xhi ? T(g.idx2) : T(0);
+  const int iw = wrap_clamp(i, g.nx, per0);
+  const T idy2 = T(g.idy2), idz2 = T(g.idz2);
+  // red at (i, j, k) when i + j + k is even
+  const bool even0 = ((i + j0) & 1) == 0;
+  auto aym = [&](int j) -> T { return (j > 1 || per1) ? idy2 : T(0); };
+  auto ayp = [&](int j) -> T { return (j < g.ny || per1) ? idy2 : T(0); };
+  auto owny = [&](int r) -> bool { return wy * R + r >= H && wy * R + r < ROWS - H && j0 + r <= g.ny; };
+  // diagonal a_c and relaxation factor omega / a_c of row r's cell with both
+  // z neighbours (d2, w2) or one (d1, w1)
+  T d1[R], d2[R], w1[R], w2[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int j = j0 + r;
+    const double dxy = ((xlo ? g.idx2 : 0.0) + (xhi ? g.idx2 : 0.0)) +
+                       (((j > 1 || per1) ? g.idy2 : 0.0) + ((j < g.ny || per1) ? g.idy2 : 0.0));
+    d2[r] = T(dxy + (g.idz2 + g.idz2));
+    d1[r] = T(dxy + g.idz2);
+    w2[r] = T(omega / (dxy + (g.idz2 + g.idz2)));
+    w1[r] = T(omega / (dxy + g.idz2));
+  }
+  // FAST: every plane of the step has both z neighbours
+  auto coef = [&](auto FASTc, int r, int k, T& d, T& w) {
+    if constexpr (decltype(FASTc)::value) {
+      d = d2[r];
+      w = w2[r];
+    } else {
+      const bool both = (k > 1 || per2) && (k < g.nz || per2);
+      d = both ? d2[r] : d1[r];
+      w = both ? w2[r] : w1[r];
+    }
+  };
+
+  unsigned off[R];  // byte offset of the loaded cell in its plane
+#pragma unroll
+  for (int r = 0; r < R; r++)
+    off[r] = (unsigned)((long)wrap_clamp(j0 + r, g.ny, per1) * g.sx + iw) * (unsigned)sizeof(T);
+
+  // LDS: this wave's top / bottom rows, and the rows above / below it (its
+  // own edge row at the workgroup's ends, where the value is never used)
+  const int e_top = (wy * 2) * kLanes + tx;
+  const int e_bot = e_top + kLanes;
+  const int e_above = wy > 0 ? e_top - kLanes : e_top;
+  const int e_below = wy < kWaves - 1 ? e_bot + kLanes : e_bot;
+  auto ebuf = [&](int q, int par) -> T* { return E + (q * 2 + par) * kEdge; };
+
+  auto plane_of = [&](int k) -> long {
+    int kw = k;
+    if (per2) kw += (kw < 1 ? g.nz : 0) - (kw > g.nz ? g.nz : 0);
+    kw = kw < 1 ? 1 : (kw > g.nz ? g.nz : kw);
+    return (long)kw * g.sxy;
+  };
+
+  const int Lbeg = z0 + 2 - 2 * NS;
+  const int Lend = z1 + 2 * NS;
+
+  // rings: slot (S + q) & 3 holds plane L - 2 + q at a step with L % 4 == S
+  // relative to Lbeg; planes L and L + 1 may still be in flight
+  T P[4][R], Q[4][R];
+  T hC[R], hD[R];                       // rhs at L - 3, L - 4
+  T X1a[R], X1b[R], Ma[R], Mb[R];       // first sweep: red at L-3, L-2; iterate at L-4, L-3
+  T X2a[R], X2b[R];                     // second sweep: red at L-5, L-4
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const long pl = plane_of(Lbeg - 2 + q);
+    const T* bp = p_in + pl;
+    const T* br = rhs + pl;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      P[q][r] = ZIN ? T(0) : ld_at(bp, off[r]);
+      Q[q][r] = ld_at(br, off[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    hC[r] = hD[r] = X1a[r] = X1b[r] = Ma[r] = Mb[r] = X2a[r] = X2b[r] = T(0);
+  }
+
+  auto zcoef = [&](auto FASTc, int k, T& azm, T& azp) {
+    if constexpr (decltype(FASTc)::value) {
+      azm = azp = idz2;
+    } else {
+      azm = (k > 1 || per2) ? idz2 : T(0);
+      azp = (k < g.nz || per2) ? idz2 : T(0);
+    }
+  };
+
+  auto step = [&](auto Sc, auto Fc, int L) {
+    constexpr int S = decltype(Sc)::value;
+    constexpr int SP = S & 1;
+    T(&pm2)[R] = P[S];
+    T(&pm1)[R] = P[(S + 1) & 3];
+    T(&p0)[R] = P[(S + 2) & 3];
+    T(&qm2)[R] = Q[S];
+    T(&qm1)[R] = Q[(S + 1) & 3];
+
+    // the input plane's edge rows
+    ebuf(0, SP)[e_top] = pm1[0];
+    ebuf(0, SP)[e_bot] = pm1[R - 1];
+    lds_barrier();
+    const T inA = ebuf(0, SP)[e_above], inB = ebuf(0, SP)[e_below];
+    const T x1A = ebuf(1, SP ^ 1)[e_above], x1B = ebuf(1, SP ^ 1)[e_below];
+
+    // A: residual of the input and red update at plane a = L - 1
+    T X1n[R];
+    {
+      const int a = L - 1;
+      T azm, azp;
+      zcoef(Fc, a, azm, azp);
+      const bool in_chunk = a >= z0 && a <= z1;
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const T pc = pm1[r];
+        const T ps = r > 0 ? pm1[r - 1] : inA;
+        const T pn = r < R - 1 ? pm1[r + 1] : inB;
+        T dg, wg;
+        coef(Fc, r, a, dg, wg);
+        const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, pm2[r], p0[r], axm, axp, aym(j0 + r),
+                              ayp(j0 + r), azm, azp, dg) -
+                      qm1[r];
+        if (in_chunk && owny(r) && ownx) acc1 += (double)res * (double)res;
+        const bool red = ((r + a) & 1) ? !even0 : even0;
+        X1n[r] = red ? fmaT(wg, res, pc) : pc;
+      }
+    }
+    // B: black update at plane b = L - 2 (the first sweep's iterate)
+    T Mn[R];
+    {
+      const int b = L - 2;
+      T azm, azp;
+      zcoef(Fc, b, azm, azp);
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const T pc = X1b[r];
+        const T ps = r > 0 ? X1b[r - 1] : x1A;
+        const T pn = r < R - 1 ? X1b[r + 1] : x1B;
+        T dg, wg;
+        coef(Fc, r, b, dg, wg);
+        const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, X1a[r], X1n[r], axm, axp, aym(j0 + r),
+                              ayp(j0 + r), azm, azp, dg) -
+                      qm2[r];
+        const bool red = ((r + b) & 1) ? !even0 : even0;
+        Mn[r] = red ? pc : fmaT(wg, res, pc);
+      }
+      if constexpr (NS == 1) {
+        if (write && b >= z0 && b <= z1) {
+          T* bo = p_out + (long)b * g.sxy;
+#pragma unroll
+          for (int r = 0; r < R; r++)
+            if (owny(r) && ownx) st_at(bo, off[r], Mn[r]);
+        }
+      }
+    }
+    if constexpr (NS == 2) {
+      const T mA = ebuf(2, SP ^ 1)[e_above], mB = ebuf(2, SP ^ 1)[e_below];
+      const T x2A = ebuf(3, SP ^ 1)[e_above], x2B = ebuf(3, SP ^ 1)[e_below];
+      // C: residual of the first sweep's iterate and red update at c = L - 3
+      T X2n[R];
+      {
+        const int c = L - 3;
+        T azm, azp;
+        zcoef(Fc, c, azm, azp);
+        const bool in_chunk = c >= z0 && c <= z1;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          const T pc = Mb[r];
+          const T ps = r > 0 ? Mb[r - 1] : mA;
+          const T pn = r < R - 1 ? Mb[r + 1] : mB;
+          T dg, wg;
+          coef(Fc, r, c, dg, wg);
+          const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, Ma[r], Mn[r], axm, axp, aym(j0 + r),
+                                ayp(j0 + r), azm, azp, dg) -
+                        hC[r];
+          if (in_chunk && owny(r) && ownx) acc2 += (double)res * (double)res;
+          const bool red = ((r + c) & 1) ? !even0 : even0;
+          X2n[r] = red ? fmaT(wg, res, pc) : pc;
+        }
+      }
+      // D: black update at d = L - 4, written out
+      {
+        const int d = L - 4;
+        T azm, azp;
+        zcoef(Fc, d, azm, azp);
+        T out[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+          const T pc = X2b[r];
+          const T ps = r > 0 ? X2b[r - 1] : x2A;
+          const T pn = r < R - 1 ? X2b[r + 1] : x2B;
+          T dg, wg;
+          coef(Fc, r, d, dg, wg);
+          const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, X2a[r], X2n[r], axm, axp, aym(j0 + r),
+                                ayp(j0 + r), azm, azp, dg) -
+                        hD[r];
+          const bool red = ((r + d) & 1) ? !even0 : even0;
+          out[r] = red ? pc : fmaT(wg, res, pc);
+        }
+        if (write && d >= z0 && d <= z1) {
+          T* bo = p_out + (long)d * g.sxy;
+#pragma unroll
+          for (int r = 0; r < R; r++)
+            if (owny(r) && ownx) st_at(bo, off[r], out[r]);
+        }
+      }
+      ebuf(2, SP)[e_top] = Mn[0];
+      ebuf(2, SP)[e_bot] = Mn[R - 1];
+      ebuf(3, SP)[e_top] = X2n[0];
+      ebuf(3, SP)[e_bot] = X2n[R - 1];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        Ma[r] = Mb[r];
+        Mb[r] = Mn[r];
+        X2a[r] = X2b[r];
+        X2b[r] = X2n[r];
+        hD[r] = hC[r];
+        hC[r] = qm2[r];
+      }
+    }
+    ebuf(1, SP)[e_top] = X1n[0];
+    ebuf(1, SP)[e_bot] = X1n[R - 1];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      X1a[r] = X1b[r];
+      X1b[r] = X1n[r];
+    }
+    // refill the dead ring slots with plane L + 2
+    const long pl = plane_of(L + 2);
+    const T* bp = p_in + pl;
+    const T* br = rhs + pl;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      pm2[r] = ZIN ? T(0) : ld_at(bp, off[r]);
+      qm2[r] = ld_at(br, off[r]);
+    }
+  };
+
+  // Trips of four steps; steps past Lend touch no output or residual.  A
+  // trip whose stage planes all lie strictly inside the domain in z (every
+  // trip on a periodic axis) takes the constant z coefficients.
+  const int fast_lo = per2 ? INT_MIN : 2 * NS + 2;  // first step with all stage planes >= 2
+  const int fast_hi = per2 ? INT_MAX : g.nz;        // last step with all stage planes <= nz - 1
+  using F0 = std::integral_constant<int, 0>;
+  using F1 = std::integral_constant<int, 1>;
+  using F2 = std::integral_constant<int, 2>;
+  using F3 = std::integral_constant<int, 3>;
+  using FAST = std::true_type;
+  using GEN = std::false_type;
+  for (int L = Lbeg; L <= Lend; L += 4) {
+    if (L >= fast_lo && L + 3 <= fast_hi) {
+      step(F0{}, FAST{}, L);
+      step(F1{}, FAST{}, L + 1);
+      step(F2{}, FAST{}, L + 2);
+      step(F3{}, FAST{}, L + 3);
+    } else {
+      step(F0{}, GEN{}, L);
+      step(F1{}, GEN{}, L + 1);
+      step(F2{}, GEN{}, L + 2);
+      step(F3{}, GEN{}, L + 3);
+    }
+  }
+}
+
+// One pass of NS sweeps with first sweep index m (input iterate m - 1).
+// With part == nullptr the pass is forced: it runs whatever the done flag
+// says and applies no stop rule (the host uses it to materialise an
+// iterate a two-sweep pass held only in registers).
+#ifndef NS_PASS_MINW
+#define NS_PASS_MINW 1
+#endif
+template <class T, int NS, int R, bool ZIN>
+__global__ void __launch_bounds__(kLanes * kWaves, NS_PASS_MINW)
+k_sor_pass(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restrict__ rhs, Geo g, Ctl* ctl,
+           double* part, double omega, int m, int itermax, int write, int inner, int zc, int ntx, int nty,
+           int ntiles) {
+  __shared__ T E[2 * NS * 2 * kEdge];
+  __shared__ double shred[16];
+  __shared__ int sh_last;
+  if (part != nullptr && ctl->done) return;
+  double acc1 = 0.0, acc2 = 0.0;
+  // edge rows a step reads before this tile wrote them hold finite values
+  for (int q = flat_tid(); q < 2 * NS * 2 * kEdge; q += kLanes * kWaves) E[q] = T(0);
+  __syncthreads();
+
+  // Persistent loop over tiles, split into 8 contiguous ranges, one per
+  // XCD (workgroup b runs on XCD b % 8).
+  const int G = gridDim.x;
+  const bool by_xcd = G >= 8;
+  const int xcd = by_xcd ? (blockIdx.x & 7) : 0;
+  const int slot = by_xcd ? (blockIdx.x >> 3) : blockIdx.x;
+  const int nwg_x = by_xcd ? (G >> 3) + (xcd < (G & 7) ? 1 : 0) : G;
+  const int lo = by_xcd ? (int)((long)ntiles * xcd / 8) : 0;
+  const int hi = by_xcd ? (int)((long)ntiles * (xcd + 1) / 8) : ntiles;
+  for (int tile = lo + slot; tile < hi; tile += nwg_x) {
+    pass_tile<T, NS, R, ZIN>(p_in, p_out, rhs, g, omega, write, tile, zc, ntx, nty, E, acc1, acc2);
+    __syncthreads();
+  }
+  if (part == nullptr) return;
+
+  const long n = (long)g.nx * g.ny * g.nz;
+  const double s1 = block_sum(acc1, shred);
+  const double s2 = NS == 2 ? block_sum(acc2, shred) : 0.0;
+  if (NS == 2 && flat_tid() == 0) part[G + blockIdx.x] = s2;
+  if (publish_partial(part, blockIdx.x, s1, ctl, G, &sh_last)) {
+    const double t1 = sum_partials(part, G, shred);
+    const double t2 = NS == 2 ? sum_partials(part + G, G, shred) : 0.0;
+    if (flat_tid() == 0) {
+      const double thr = inner ? ctl->thr_in : ctl->thr;
+      // sweep mm + 1 reports the residual of iterate mm
+      auto check = [&](int mm, double tot) -> bool {
+        const double res = sqrt(tot / (double)n);
+        if (!(mm >= 1 || itermax == 0)) return false;
+        if (inner) ctl->res_in = res; else ctl->res = res;
+        const bool fin = isfinite(res);
+        if (!(res > thr) || mm >= itermax || !fin) {
+          ctl->done = 1;
+          ctl->final_ = mm;
+          if (!fin) ctl->nonfinite = 1;
+          return true;
+        }
+        return false;
+      };
+      if (!check(m - 1, t1) && NS == 2) check(m, t2);
+      ctl->ticket = 0;
+    }
+  }
+}
+
+template <class T, int NS, int R>
+int pass_resident() {
+  static int cached = 0;
+  if (cached > 0) return cached;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sor_pass<T, NS, R, false>, kLanes * kWaves, 0) !=
+      hipSuccess)
+    return 0;
+  cached = cus * (per_cu > 0 ? per_cu : 1);
+  return cached;
+}
+
+template <class T, int NS, int R>
+hipError_t launch_r(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl, double* part,
+                    double omega, int m, int itermax, int write, int zero_in, int inner, int zc) {
+  constexpr int H = 2 * NS;
+  const int ntx = (g.nx + (kLanes - 2 * H) - 1) / (kLanes - 2 * H);
+  const int nty = (g.ny + (R * kWaves - 2 * H) - 1) / (R * kWaves - 2 * H);
+  const int ntz = (g.nz + zc - 1) / zc;
+  const int ntiles = ntx * nty * ntz;
+  int nb = pass_resident<T, NS, R>();
+  if (nb <= 0 || nb > ntiles) nb = ntiles;
+  const dim3 blk(kLanes, kWaves);
+  if (zero_in)
+    k_sor_pass<T, NS, R, true><<<nb, blk, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write, inner,
+                                                   zc, ntx, nty, ntiles);
+  else
+    k_sor_pass<T, NS, R, false><<<nb, blk, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write,
+                                                    inner, zc, ntx, nty, ntiles);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool pass_shape_ok(const SorShape& s) { return s.ty == 16 || s.ty == 24 || s.ty == 32; }
+
+bool pass_grid_ok(const Geo& g, size_t esz) {
+  // one wrap of the 4-cell halo on periodic axes; plane offsets in 32 bits
+  for (int a = 0; a < 3; a++) {
+    const int n = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+    if (g.per[a] && n < 4) return false;
+  }
+  return (double)g.sxy * (double)esz < 2147483648.0;
+}
+
+int pass_max_partials(const Geo& g) {
+  // resident workgroups never exceed the tile count of the smallest tiles
+  const int ntx = (g.nx + 55) / 56, nty = (g.ny + 7) / 8;
+  return 2 * ntx * nty * g.nz;
+}
+
+int pass_resident_groups(int ty, bool f32, int ns) {
+  const int R = ty / kWaves;
+  if (ns == 1) {
+    switch (R) {
+      case 2: return f32 ? pass_resident<float, 1, 2>() : pass_resident<double, 1, 2>();
+      case 3: return f32 ? pass_resident<float, 1, 3>() : pass_resident<double, 1, 3>();
+      case 4: return f32 ? pass_resident<float, 1, 4>() : pass_resident<double, 1, 4>();
+    }
+  } else {
+    switch (R) {
+      case 2: return f32 ? pass_resident<float, 2, 2>() : pass_resident<double, 2, 2>();
+      case 3: return f32 ? pass_resident<float, 2, 3>() : pass_resident<double, 2, 3>();
+      case 4: return f32 ? pass_resident<float, 2, 4>() : pass_resident<double, 2, 4>();
+    }
+  }
+  return 0;
+}
+
+int pass_columns(const Geo& g, int ty, int ns) {
+  const int h = 2 * ns;
+  return ((g.nx + (kLanes - 2 * h) - 1) / (kLanes - 2 * h)) * ((g.ny + (ty - 2 * h) - 1) / (ty - 2 * h));
+}
+
+template <class T>
+hipError_t launch_sor_pass(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl,
+                           double* part, double omega, int m, int itermax, int write, int zero_in, int inner,
+                           int ns, const SorShape& s) {
+  const int zc = s.zc > 0 ? (s.zc < g.nz ? s.zc : g.nz) : g.nz;
+  const int R = s.ty / kWaves;
+  if (ns == 1) {
+    switch (R) {
+      case 2: return launch_r<T, 1, 2>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+      case 3: return launch_r<T, 1, 3>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+      case 4: return launch_r<T, 1, 4>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+    }
+  } else if (ns == 2) {
+    switch (R) {
+      case 2: return launch_r<T, 2, 2>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+      case 3: return launch_r<T, 2, 3>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+      case 4: return launch_r<T, 2, 4>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_sor_pass<double>(hipStream_t, const Geo&, const double*, double*, const double*, Ctl*,
+                                            double*, double, int, int, int, int, int, int, const SorShape&);
+template hipError_t launch_sor_pass<float>(hipStream_t, const Geo&, const float*, float*, const float*, Ctl*,
+                                           double*, double, int, int, int, int, int, int, const SorShape&);
+
+}  // namespace ns
