@@ -28,6 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_1201_2118_amd", "csrc")
+# sources that define the sweep kernels (a traffic figure is only reported
+# for the exact kernel its counters were taken on)
+SWEEP_SOURCES = ("sor_pass.hip", "sor_fused.hip", "ns_internal.h", "reduce.h")
 METRIC = "Mcell-steps/s and HBM GB/s, 512^3 NS step, FP32-mixed vs FP64 on 1 GPU"
 
 
@@ -112,6 +117,38 @@ def measure_batched(steps):
             "precision": "mixed", "dt": "adaptive (tau 0.5)"}
 
 
+def sweep_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_tag, tile):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary (FETCH_SIZE and WRITE_SIZE runs, calibrated by a plain copy),
+    or None when the summary was taken on other kernel sources or shape."""
+    path = os.path.join(PROFILES, f"{kernel_tag}_cavity512_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != sweep_source_hash():
+        return None
+    if [int(x) for x in kv.get("tile", "0 0").split()] != list(tile):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def step_bytes(n, sweeps, mixed, outers=1):
     """Algorithmic HBM bytes of one step per cell (minimum single pass per
     stage): FP64 112 + 24 S; mixed 60 + 12 S + 28 O."""
@@ -192,10 +229,17 @@ def main():
         res[form] = r
     head = res.get("mixed") or res["fp64"]
     dom = head
+    f32 = head is res.get("mixed")
+    per_launch = 2 if dom["tile"][0] >= 16 else 1
+    tag = ("sor_pass" if per_launch == 2 else "sor_fused") + ("_f32" if f32 else "_f64")
+    traffic = traffic_from_profile(tag, dom["tile"]) if args.n == 512 else None
     roof = {"bound": "hbm", "achieved": round(dom["sor_gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(dom["sor_gbs"] / PEAK_HBM_GBS, 4), "traffic": None,
-            "kernel": "red-black SOR sweep (%s)" % ("FP32" if head is res.get("mixed") else "FP64"),
+            "frac": round(dom["sor_gbs"] / PEAK_HBM_GBS, 4),
+            "traffic": round(traffic) if traffic else None,
+            "kernel": "red-black SOR, %d sweep(s) per launch (%s)" % (per_launch, "FP32" if f32 else "FP64"),
+            "sweeps_per_launch": per_launch,
             "bytes_per_launch": dom["sor_bytes_per_launch"], "avg_launch_ms": round(dom["sor_avg_ms"], 5),
+            "sweep_equivalent_gbs": round(per_launch * dom["sor_gbs"], 1),
             "tile": dom["tile"]}
     out = {
         "metric": METRIC,

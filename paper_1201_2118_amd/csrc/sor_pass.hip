@@ -44,7 +44,7 @@ namespace ns {
 namespace {
 
 constexpr int kLanes = 64;  // x positions per row (one wave)
-constexpr int kWaves = 8;   // waves per workgroup, stacked in y
+constexpr int kRows = 2;    // rows per lane
 
 __device__ __forceinline__ int dpp_left(int v) {  // lane l receives lane l - 1 (0 at lane 0)
   return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
@@ -100,27 +100,40 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Global-memory pointers and a plane's base pointer, opaque to the
+// optimiser: it keeps it from folding the per-lane offset into a hoisted
+// 64-bit per-lane address, so loads and stores use the scalar-base +
+// 32-bit-offset form.
+#define NS_GLOBAL __attribute__((address_space(1)))
 template <class T>
-__device__ __forceinline__ T ld_at(const T* base, unsigned off) {
-  return *(const T*)((const char*)base + off);
+__device__ __forceinline__ NS_GLOBAL T* plane_ptr(T* p, long elems) {
+  NS_GLOBAL T* q = (NS_GLOBAL T*)(p + elems);
+  asm volatile("" : "+s"(q));
+  return q;
+}
+
+template <class T>
+__device__ __forceinline__ T ld_at(const NS_GLOBAL T* base, unsigned off) {
+  return *(const NS_GLOBAL T*)((const NS_GLOBAL char*)base + off);
 }
 template <class T>
-__device__ __forceinline__ void st_at(T* base, unsigned off, T v) {
-  *(T*)((char*)base + off) = v;
+__device__ __forceinline__ void st_at(NS_GLOBAL T* base, unsigned off, T v) {
+  *(NS_GLOBAL T*)((NS_GLOBAL char*)base + off) = v;
 }
 
 // LDS edge rows: per quantity and step parity, two rows (top, bottom) per
 // wave.
-constexpr int kEdge = kWaves * 2 * kLanes;
+template <int W>
+constexpr int kEdge = W * 2 * kLanes;
 
-template <class T, int NS, int R, bool ZIN>
+template <class T, int NS, int R, int W, bool ZIN>
 __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restrict__ p_out,
                                           const T* __restrict__ rhs, const Geo& g, double omega, int write,
                                           int tile, int zc, int ntx, int nty, T* __restrict__ E, double& acc1,
                                           double& acc2) {
   constexpr int H = 2 * NS;
   constexpr int TX = kLanes - 2 * H;
-  constexpr int ROWS = R * kWaves;
+  constexpr int ROWS = R * W;
   constexpr int TY = ROWS - 2 * H;
   const int tx = threadIdx.x;
   const int wy = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
@@ -146,17 +159,20 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   auto ayp = [&](int j) -> T { return (j < g.ny || per1) ? idy2 : T(0); };
   auto owny = [&](int r) -> bool { return wy * R + r >= H && wy * R + r < ROWS - H && j0 + r <= g.ny; };
   // diagonal a_c and relaxation factor omega / a_c of row r's cell with both
-  // z neighbours (d2, w2) or one (d1, w1)
+  // z neighbours (d2, w2) or one (d1, w1, planes next to a z wall)
+  auto dxy_of = [&](int j) -> double {
+    return ((xlo ? g.idx2 : 0.0) + (xhi ? g.idx2 : 0.0)) +
+           (((j > 1 || per1) ? g.idy2 : 0.0) + ((j < g.ny || per1) ? g.idy2 : 0.0));
+  };
   T d1[R], d2[R], w1[R], w2[R];
 #pragma unroll
   for (int r = 0; r < R; r++) {
-    const int j = j0 + r;
-    const double dxy = ((xlo ? g.idx2 : 0.0) + (xhi ? g.idx2 : 0.0)) +
-                       (((j > 1 || per1) ? g.idy2 : 0.0) + ((j < g.ny || per1) ? g.idy2 : 0.0));
-    d2[r] = T(dxy + (g.idz2 + g.idz2));
-    d1[r] = T(dxy + g.idz2);
-    w2[r] = T(omega / (dxy + (g.idz2 + g.idz2)));
-    w1[r] = T(omega / (dxy + g.idz2));
+    const double dd = dxy_of(j0 + r) + (g.idz2 + g.idz2);
+    d2[r] = T(dd);
+    w2[r] = T(omega / dd);
+    const double d1d = dxy_of(j0 + r) + g.idz2;
+    d1[r] = T(d1d);
+    w1[r] = T(omega / d1d);
   }
   // FAST: every plane of the step has both z neighbours
   auto coef = [&](auto FASTc, int r, int k, T& d, T& w) {
@@ -180,8 +196,8 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   const int e_top = (wy * 2) * kLanes + tx;
   const int e_bot = e_top + kLanes;
   const int e_above = wy > 0 ? e_top - kLanes : e_top;
-  const int e_below = wy < kWaves - 1 ? e_bot + kLanes : e_bot;
-  auto ebuf = [&](int q, int par) -> T* { return E + (q * 2 + par) * kEdge; };
+  const int e_below = wy < W - 1 ? e_bot + kLanes : e_bot;
+  auto ebuf = [&](int q, int par) -> T* { return E + (q * 2 + par) * kEdge<W>; };
 
   auto plane_of = [&](int k) -> long {
     int kw = k;
@@ -202,8 +218,8 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     const long pl = plane_of(Lbeg - 2 + q);
-    const T* bp = p_in + pl;
-    const T* br = rhs + pl;
+    const NS_GLOBAL T* bp = plane_ptr(p_in, pl);
+    const NS_GLOBAL T* br = plane_ptr(rhs, pl);
 #pragma unroll
     for (int r = 0; r < R; r++) {
       P[q][r] = ZIN ? T(0) : ld_at(bp, off[r]);
@@ -283,7 +299,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
       }
       if constexpr (NS == 1) {
         if (write && b >= z0 && b <= z1) {
-          T* bo = p_out + (long)b * g.sxy;
+          NS_GLOBAL T* bo = plane_ptr(p_out, (long)b * g.sxy);
 #pragma unroll
           for (int r = 0; r < R; r++)
             if (owny(r) && ownx) st_at(bo, off[r], Mn[r]);
@@ -293,7 +309,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
     if constexpr (NS == 2) {
       const T mA = ebuf(2, SP ^ 1)[e_above], mB = ebuf(2, SP ^ 1)[e_below];
       const T x2A = ebuf(3, SP ^ 1)[e_above], x2B = ebuf(3, SP ^ 1)[e_below];
-      // C: residual of the first sweep's iterate and red update at c = L - 3
+        // C: residual of the first sweep's iterate and red update at c = L - 3
       T X2n[R];
       {
         const int c = L - 3;
@@ -315,7 +331,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
           X2n[r] = red ? fmaT(wg, res, pc) : pc;
         }
       }
-      // D: black update at d = L - 4, written out
+        // D: black update at d = L - 4, written out
       {
         const int d = L - 4;
         T azm, azp;
@@ -335,7 +351,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
           out[r] = red ? pc : fmaT(wg, res, pc);
         }
         if (write && d >= z0 && d <= z1) {
-          T* bo = p_out + (long)d * g.sxy;
+          NS_GLOBAL T* bo = plane_ptr(p_out, (long)d * g.sxy);
 #pragma unroll
           for (int r = 0; r < R; r++)
             if (owny(r) && ownx) st_at(bo, off[r], out[r]);
@@ -364,8 +380,8 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
     }
     // refill the dead ring slots with plane L + 2
     const long pl = plane_of(L + 2);
-    const T* bp = p_in + pl;
-    const T* br = rhs + pl;
+    const NS_GLOBAL T* bp = plane_ptr(p_in, pl);
+    const NS_GLOBAL T* br = plane_ptr(rhs, pl);
 #pragma unroll
     for (int r = 0; r < R; r++) {
       pm2[r] = ZIN ? T(0) : ld_at(bp, off[r]);
@@ -406,18 +422,18 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
 #ifndef NS_PASS_MINW
 #define NS_PASS_MINW 1
 #endif
-template <class T, int NS, int R, bool ZIN>
-__global__ void __launch_bounds__(kLanes * kWaves, NS_PASS_MINW)
+template <class T, int NS, int R, int W, bool ZIN>
+__global__ void __launch_bounds__(kLanes * W, NS_PASS_MINW)
 k_sor_pass(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restrict__ rhs, Geo g, Ctl* ctl,
            double* part, double omega, int m, int itermax, int write, int inner, int zc, int ntx, int nty,
            int ntiles) {
-  __shared__ T E[2 * NS * 2 * kEdge];
+  __shared__ T E[2 * NS * 2 * kEdge<W>];
   __shared__ double shred[16];
   __shared__ int sh_last;
   if (part != nullptr && ctl->done) return;
   double acc1 = 0.0, acc2 = 0.0;
   // edge rows a step reads before this tile wrote them hold finite values
-  for (int q = flat_tid(); q < 2 * NS * 2 * kEdge; q += kLanes * kWaves) E[q] = T(0);
+  for (int q = flat_tid(); q < 2 * NS * 2 * kEdge<W>; q += kLanes * W) E[q] = T(0);
   __syncthreads();
 
   // Persistent loop over tiles, split into 8 contiguous ranges, one per
@@ -430,7 +446,7 @@ k_sor_pass(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restric
   const int lo = by_xcd ? (int)((long)ntiles * xcd / 8) : 0;
   const int hi = by_xcd ? (int)((long)ntiles * (xcd + 1) / 8) : ntiles;
   for (int tile = lo + slot; tile < hi; tile += nwg_x) {
-    pass_tile<T, NS, R, ZIN>(p_in, p_out, rhs, g, omega, write, tile, zc, ntx, nty, E, acc1, acc2);
+    pass_tile<T, NS, R, W, ZIN>(p_in, p_out, rhs, g, omega, write, tile, zc, ntx, nty, E, acc1, acc2);
     __syncthreads();
   }
   if (part == nullptr) return;
@@ -464,38 +480,50 @@ k_sor_pass(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restric
   }
 }
 
-template <class T, int NS, int R>
+template <class T, int NS, int W>
 int pass_resident() {
   static int cached = 0;
   if (cached > 0) return cached;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sor_pass<T, NS, R, false>, kLanes * kWaves, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sor_pass<T, NS, kRows, W, false>, kLanes * W, 0) !=
       hipSuccess)
     return 0;
   cached = cus * (per_cu > 0 ? per_cu : 1);
   return cached;
 }
 
-template <class T, int NS, int R>
-hipError_t launch_r(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl, double* part,
+template <class T, int NS, int W>
+hipError_t launch_w(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl, double* part,
                     double omega, int m, int itermax, int write, int zero_in, int inner, int zc) {
   constexpr int H = 2 * NS;
+  constexpr int ROWS = kRows * W;
   const int ntx = (g.nx + (kLanes - 2 * H) - 1) / (kLanes - 2 * H);
-  const int nty = (g.ny + (R * kWaves - 2 * H) - 1) / (R * kWaves - 2 * H);
+  const int nty = (g.ny + (ROWS - 2 * H) - 1) / (ROWS - 2 * H);
   const int ntz = (g.nz + zc - 1) / zc;
   const int ntiles = ntx * nty * ntz;
-  int nb = pass_resident<T, NS, R>();
+  int nb = pass_resident<T, NS, W>();
   if (nb <= 0 || nb > ntiles) nb = ntiles;
-  const dim3 blk(kLanes, kWaves);
+  const dim3 blk(kLanes, W);
   if (zero_in)
-    k_sor_pass<T, NS, R, true><<<nb, blk, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write, inner,
-                                                   zc, ntx, nty, ntiles);
+    k_sor_pass<T, NS, kRows, W, true><<<nb, blk, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write,
+                                                          inner, zc, ntx, nty, ntiles);
   else
-    k_sor_pass<T, NS, R, false><<<nb, blk, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write,
-                                                    inner, zc, ntx, nty, ntiles);
+    k_sor_pass<T, NS, kRows, W, false><<<nb, blk, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write,
+                                                           inner, zc, ntx, nty, ntiles);
   return hipGetLastError();
+}
+
+template <class T, int NS>
+hipError_t launch_ns(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl, double* part,
+                     double omega, int m, int itermax, int write, int zero_in, int inner, int zc, int rows) {
+  switch (rows) {
+    case 16: return launch_w<T, NS, 8>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+    case 24: return launch_w<T, NS, 12>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+    case 32: return launch_w<T, NS, 16>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -503,7 +531,7 @@ hipError_t launch_r(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const
 bool pass_shape_ok(const SorShape& s) { return s.ty == 16 || s.ty == 24 || s.ty == 32; }
 
 bool pass_grid_ok(const Geo& g, size_t esz) {
-  // one wrap of the 4-cell halo on periodic axes; plane offsets in 32 bits
+  // one wrap of the 4-cell halo on periodic axes; plane offsets in 31 bits
   for (int a = 0; a < 3; a++) {
     const int n = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
     if (g.per[a] && n < 4) return false;
@@ -518,19 +546,13 @@ int pass_max_partials(const Geo& g) {
 }
 
 int pass_resident_groups(int ty, bool f32, int ns) {
-  const int R = ty / kWaves;
-  if (ns == 1) {
-    switch (R) {
-      case 2: return f32 ? pass_resident<float, 1, 2>() : pass_resident<double, 1, 2>();
-      case 3: return f32 ? pass_resident<float, 1, 3>() : pass_resident<double, 1, 3>();
-      case 4: return f32 ? pass_resident<float, 1, 4>() : pass_resident<double, 1, 4>();
-    }
-  } else {
-    switch (R) {
-      case 2: return f32 ? pass_resident<float, 2, 2>() : pass_resident<double, 2, 2>();
-      case 3: return f32 ? pass_resident<float, 2, 3>() : pass_resident<double, 2, 3>();
-      case 4: return f32 ? pass_resident<float, 2, 4>() : pass_resident<double, 2, 4>();
-    }
+  switch (ty) {
+    case 16: return ns == 1 ? (f32 ? pass_resident<float, 1, 8>() : pass_resident<double, 1, 8>())
+                            : (f32 ? pass_resident<float, 2, 8>() : pass_resident<double, 2, 8>());
+    case 24: return ns == 1 ? (f32 ? pass_resident<float, 1, 12>() : pass_resident<double, 1, 12>())
+                            : (f32 ? pass_resident<float, 2, 12>() : pass_resident<double, 2, 12>());
+    case 32: return ns == 1 ? (f32 ? pass_resident<float, 1, 16>() : pass_resident<double, 1, 16>())
+                            : (f32 ? pass_resident<float, 2, 16>() : pass_resident<double, 2, 16>());
   }
   return 0;
 }
@@ -545,20 +567,8 @@ hipError_t launch_sor_pass(hipStream_t st, const Geo& g, const T* p_in, T* p_out
                            double* part, double omega, int m, int itermax, int write, int zero_in, int inner,
                            int ns, const SorShape& s) {
   const int zc = s.zc > 0 ? (s.zc < g.nz ? s.zc : g.nz) : g.nz;
-  const int R = s.ty / kWaves;
-  if (ns == 1) {
-    switch (R) {
-      case 2: return launch_r<T, 1, 2>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
-      case 3: return launch_r<T, 1, 3>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
-      case 4: return launch_r<T, 1, 4>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
-    }
-  } else if (ns == 2) {
-    switch (R) {
-      case 2: return launch_r<T, 2, 2>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
-      case 3: return launch_r<T, 2, 3>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
-      case 4: return launch_r<T, 2, 4>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
-    }
-  }
+  if (ns == 1) return launch_ns<T, 1>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc, s.ty);
+  if (ns == 2) return launch_ns<T, 2>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc, s.ty);
   return hipErrorInvalidValue;
 }
 
