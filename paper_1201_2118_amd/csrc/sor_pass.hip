@@ -85,8 +85,8 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 template <class T>
 __device__ __forceinline__ T stencil(T pc, T pw, T pe, T ps, T pn, T pd, T pu, T axm, T axp, T aym, T ayp,
                                      T azm, T azp, T diag) {
-  T t = axm * pw;
-  t = fmaT(axp, pe, t);
+  T t = pw * axm;
+  t = fmaT(pe, axp, t);
   t = fmaT(aym, ps, t);
   t = fmaT(ayp, pn, t);
   t = fmaT(azm, pd, t);
@@ -100,25 +100,26 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Global-memory pointers and a plane's base pointer, opaque to the
-// optimiser: it keeps it from folding the per-lane offset into a hoisted
-// 64-bit per-lane address, so loads and stores use the scalar-base +
-// 32-bit-offset form.
+// One z plane of a field: a global pointer made opaque to the optimiser,
+// which keeps it from folding the per-lane offset into a hoisted 64-bit
+// per-lane address (loads then take the scalar base + 32-bit offset form).
 #define NS_GLOBAL __attribute__((address_space(1)))
+struct Plane {
+  NS_GLOBAL char* b;
+};
 template <class T>
-__device__ __forceinline__ NS_GLOBAL T* plane_ptr(T* p, long elems) {
-  NS_GLOBAL T* q = (NS_GLOBAL T*)(p + elems);
+__device__ __forceinline__ Plane plane_at(const T* p, long elems, long) {
+  NS_GLOBAL char* q = (NS_GLOBAL char*)(p + elems);
   asm volatile("" : "+s"(q));
-  return q;
-}
-
-template <class T>
-__device__ __forceinline__ T ld_at(const NS_GLOBAL T* base, unsigned off) {
-  return *(const NS_GLOBAL T*)((const NS_GLOBAL char*)base + off);
+  return Plane{q};
 }
 template <class T>
-__device__ __forceinline__ void st_at(NS_GLOBAL T* base, unsigned off, T v) {
-  *(NS_GLOBAL T*)((NS_GLOBAL char*)base + off) = v;
+__device__ __forceinline__ T ld_plane(const Plane& b, unsigned off, T*) {
+  return *(const NS_GLOBAL T*)(b.b + off);
+}
+template <class T>
+__device__ __forceinline__ void st_plane(const Plane& b, unsigned off, T v) {
+  *(NS_GLOBAL T*)(b.b + off) = v;
 }
 
 // LDS edge rows: per quantity and step parity, two rows (top, bottom) per
@@ -153,8 +154,6 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   const T axp = xhi ? T(g.idx2) : T(0);
   const int iw = wrap_clamp(i, g.nx, per0);
   const T idy2 = T(g.idy2), idz2 = T(g.idz2);
-  // red at (i, j, k) when i + j + k is even
-  const bool even0 = ((i + j0) & 1) == 0;
   auto aym = [&](int j) -> T { return (j > 1 || per1) ? idy2 : T(0); };
   auto ayp = [&](int j) -> T { return (j < g.ny || per1) ? idy2 : T(0); };
   auto owny = [&](int r) -> bool { return wy * R + r >= H && wy * R + r < ROWS - H && j0 + r <= g.ny; };
@@ -164,25 +163,37 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
     return ((xlo ? g.idx2 : 0.0) + (xhi ? g.idx2 : 0.0)) +
            (((j > 1 || per1) ? g.idy2 : 0.0) + ((j < g.ny || per1) ? g.idy2 : 0.0));
   };
-  T d1[R], d2[R], w1[R], w2[R];
+  const int Lbeg = z0 + 2 - 2 * NS;  // first step: the ring holds planes Lbeg - 2 .. Lbeg + 1
+  const int Lend = z1 + 2 * NS;      // last step: the last stage reaches z1
+  T d1[R], d2[R], w1[R], wA[R], wB[R];
 #pragma unroll
   for (int r = 0; r < R; r++) {
     const double dd = dxy_of(j0 + r) + (g.idz2 + g.idz2);
     d2[r] = T(dd);
-    w2[r] = T(omega / dd);
     const double d1d = dxy_of(j0 + r) + g.idz2;
     d1[r] = T(d1d);
     w1[r] = T(omega / d1d);
+    // The colour is folded into the relaxation factor: wA is omega / a_c
+    // where the cell is red on planes of Lbeg's parity (0 elsewhere), wB
+    // where it is red on the other planes.  A red stage on a plane of
+    // Lbeg's parity and a black stage on the other parity use wA; a cell
+    // with weight 0 keeps its value exactly.
+    const bool redA = ((i + j0 + r + Lbeg) & 1) == 0;
+    const T w2 = T(omega / dd);
+    wA[r] = redA ? w2 : T(0);
+    wB[r] = redA ? T(0) : w2;
   }
-  // FAST: every plane of the step has both z neighbours
-  auto coef = [&](auto FASTc, int r, int k, T& d, T& w) {
+  // FAST: every plane of the step has both z neighbours.  wsel is the
+  // step's weight (wA or wB); planes next to a z wall swap in omega / a_c
+  // of the cell with one z neighbour.
+  auto coef = [&](auto FASTc, int r, int k, T wsel, T& d, T& w) {
     if constexpr (decltype(FASTc)::value) {
       d = d2[r];
-      w = w2[r];
+      w = wsel;
     } else {
       const bool both = (k > 1 || per2) && (k < g.nz || per2);
       d = both ? d2[r] : d1[r];
-      w = both ? w2[r] : w1[r];
+      w = both ? wsel : (wsel != T(0) ? w1[r] : T(0));
     }
   };
 
@@ -206,8 +217,6 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
     return (long)kw * g.sxy;
   };
 
-  const int Lbeg = z0 + 2 - 2 * NS;
-  const int Lend = z1 + 2 * NS;
 
   // rings: slot (S + q) & 3 holds plane L - 2 + q at a step with L % 4 == S
   // relative to Lbeg; planes L and L + 1 may still be in flight
@@ -218,12 +227,12 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     const long pl = plane_of(Lbeg - 2 + q);
-    const NS_GLOBAL T* bp = plane_ptr(p_in, pl);
-    const NS_GLOBAL T* br = plane_ptr(rhs, pl);
+    const Plane bp = plane_at(p_in, pl, g.sxy);
+    const Plane br = plane_at(rhs, pl, g.sxy);
 #pragma unroll
     for (int r = 0; r < R; r++) {
-      P[q][r] = ZIN ? T(0) : ld_at(bp, off[r]);
-      Q[q][r] = ld_at(br, off[r]);
+      P[q][r] = ZIN ? T(0) : ld_plane(bp, off[r], (T*)nullptr);
+      Q[q][r] = ld_plane(br, off[r], (T*)nullptr);
     }
   }
 #pragma unroll
@@ -269,13 +278,12 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
         const T ps = r > 0 ? pm1[r - 1] : inA;
         const T pn = r < R - 1 ? pm1[r + 1] : inB;
         T dg, wg;
-        coef(Fc, r, a, dg, wg);
+        coef(Fc, r, a, (S & 1) ? wA[r] : wB[r], dg, wg);
         const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, pm2[r], p0[r], axm, axp, aym(j0 + r),
                               ayp(j0 + r), azm, azp, dg) -
                       qm1[r];
         if (in_chunk && owny(r) && ownx) acc1 += (double)res * (double)res;
-        const bool red = ((r + a) & 1) ? !even0 : even0;
-        X1n[r] = red ? fmaT(wg, res, pc) : pc;
+        X1n[r] = fmaT(wg, res, pc);
       }
     }
     // B: black update at plane b = L - 2 (the first sweep's iterate)
@@ -290,19 +298,18 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
         const T ps = r > 0 ? X1b[r - 1] : x1A;
         const T pn = r < R - 1 ? X1b[r + 1] : x1B;
         T dg, wg;
-        coef(Fc, r, b, dg, wg);
+        coef(Fc, r, b, (S & 1) ? wA[r] : wB[r], dg, wg);
         const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, X1a[r], X1n[r], axm, axp, aym(j0 + r),
                               ayp(j0 + r), azm, azp, dg) -
                       qm2[r];
-        const bool red = ((r + b) & 1) ? !even0 : even0;
-        Mn[r] = red ? pc : fmaT(wg, res, pc);
+        Mn[r] = fmaT(wg, res, pc);
       }
       if constexpr (NS == 1) {
         if (write && b >= z0 && b <= z1) {
-          NS_GLOBAL T* bo = plane_ptr(p_out, (long)b * g.sxy);
+          const Plane bo = plane_at(p_out, (long)b * g.sxy, g.sxy);
 #pragma unroll
           for (int r = 0; r < R; r++)
-            if (owny(r) && ownx) st_at(bo, off[r], Mn[r]);
+            if (owny(r) && ownx) st_plane(bo, off[r], Mn[r]);
         }
       }
     }
@@ -322,13 +329,12 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
           const T ps = r > 0 ? Mb[r - 1] : mA;
           const T pn = r < R - 1 ? Mb[r + 1] : mB;
           T dg, wg;
-          coef(Fc, r, c, dg, wg);
+          coef(Fc, r, c, (S & 1) ? wA[r] : wB[r], dg, wg);
           const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, Ma[r], Mn[r], axm, axp, aym(j0 + r),
                                 ayp(j0 + r), azm, azp, dg) -
                         hC[r];
           if (in_chunk && owny(r) && ownx) acc2 += (double)res * (double)res;
-          const bool red = ((r + c) & 1) ? !even0 : even0;
-          X2n[r] = red ? fmaT(wg, res, pc) : pc;
+          X2n[r] = fmaT(wg, res, pc);
         }
       }
         // D: black update at d = L - 4, written out
@@ -343,18 +349,17 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
           const T ps = r > 0 ? X2b[r - 1] : x2A;
           const T pn = r < R - 1 ? X2b[r + 1] : x2B;
           T dg, wg;
-          coef(Fc, r, d, dg, wg);
+          coef(Fc, r, d, (S & 1) ? wA[r] : wB[r], dg, wg);
           const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, X2a[r], X2n[r], axm, axp, aym(j0 + r),
                                 ayp(j0 + r), azm, azp, dg) -
                         hD[r];
-          const bool red = ((r + d) & 1) ? !even0 : even0;
-          out[r] = red ? pc : fmaT(wg, res, pc);
+          out[r] = fmaT(wg, res, pc);
         }
         if (write && d >= z0 && d <= z1) {
-          NS_GLOBAL T* bo = plane_ptr(p_out, (long)d * g.sxy);
+          const Plane bo = plane_at(p_out, (long)d * g.sxy, g.sxy);
 #pragma unroll
           for (int r = 0; r < R; r++)
-            if (owny(r) && ownx) st_at(bo, off[r], out[r]);
+            if (owny(r) && ownx) st_plane(bo, off[r], out[r]);
         }
       }
       ebuf(2, SP)[e_top] = Mn[0];
@@ -380,20 +385,20 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
     }
     // refill the dead ring slots with plane L + 2
     const long pl = plane_of(L + 2);
-    const NS_GLOBAL T* bp = plane_ptr(p_in, pl);
-    const NS_GLOBAL T* br = plane_ptr(rhs, pl);
+    const Plane bp = plane_at(p_in, pl, g.sxy);
+    const Plane br = plane_at(rhs, pl, g.sxy);
 #pragma unroll
     for (int r = 0; r < R; r++) {
-      pm2[r] = ZIN ? T(0) : ld_at(bp, off[r]);
-      qm2[r] = ld_at(br, off[r]);
+      pm2[r] = ZIN ? T(0) : ld_plane(bp, off[r], (T*)nullptr);
+      qm2[r] = ld_plane(br, off[r], (T*)nullptr);
     }
   };
 
-  // Trips of four steps; steps past Lend touch no output or residual.  A
-  // trip whose stage planes all lie strictly inside the domain in z (every
-  // trip on a periodic axis) takes the constant z coefficients.
+  // Trips of four steps.  A trip whose stage planes all lie strictly inside
+  // the domain in z (every trip on a periodic axis) and that ends by Lend
+  // takes the constant z coefficients; the last trip stops after Lend.
   const int fast_lo = per2 ? INT_MIN : 2 * NS + 2;  // first step with all stage planes >= 2
-  const int fast_hi = per2 ? INT_MAX : g.nz;        // last step with all stage planes <= nz - 1
+  const int fast_hi = min(per2 ? INT_MAX : g.nz, Lend);  // last such step <= nz - 1, within the chunk
   using F0 = std::integral_constant<int, 0>;
   using F1 = std::integral_constant<int, 1>;
   using F2 = std::integral_constant<int, 2>;
@@ -408,8 +413,11 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
       step(F3{}, FAST{}, L + 3);
     } else {
       step(F0{}, GEN{}, L);
+      if (L + 1 > Lend) break;
       step(F1{}, GEN{}, L + 1);
+      if (L + 2 > Lend) break;
       step(F2{}, GEN{}, L + 2);
+      if (L + 3 > Lend) break;
       step(F3{}, GEN{}, L + 3);
     }
   }
