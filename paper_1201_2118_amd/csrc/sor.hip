@@ -152,20 +152,37 @@ k_defect(int zr, const double* __restrict__ p_in, const float* __restrict__ e, d
   __shared__ int sh_last;
   const long n = (long)g.nx * g.ny * g.nz;
   double acc = 0.0;
-  for_cells(g, zr, [&](int ci, int cj, int ck, long c) {
-    const Nb nb = neighbours(g, ci, cj, ck);
-    const double pc = p_in[c] + (e ? (double)e[c] : 0.0);
-    double s = 0.0;
+  // A thread marches its (i, j) column through a run of zr planes and keeps
+  // p + e of the planes below, at and above the cell in registers.
+  const int i = blockIdx.x * kCellX + threadIdx.x + 1;
+  const int j = blockIdx.y * kCellY + threadIdx.y + 1;
+  if (i <= g.nx && j <= g.ny) {
+    const Nb nb = neighbours(g, i, j, 1);  // x and y entries; z per plane below
+    const int k0 = blockIdx.z * zr + 1;
+    const int k1 = min(g.nz, k0 + zr - 1);
+    auto q = [&](long c) { return p_in[c] + (e ? (double)e[c] : 0.0); };
+    const int per2 = g.per[2];
+    auto zdn = [&](int k) -> long { return k > 1 ? -g.sxy : (per2 ? (long)(g.nz - 1) * g.sxy : 0L); };
+    auto zup = [&](int k) -> long { return k < g.nz ? g.sxy : (per2 ? -(long)(g.nz - 1) * g.sxy : 0L); };
+    long c = (long)k0 * g.sxy + (long)j * g.sx + i;
+    double qc = q(c), qd = q(c + zdn(k0));
+    for (int k = k0; k <= k1; k++, c += g.sxy) {
+      const double qu = q(c + zup(k));
+      const double azm = (k > 1 || per2) ? g.idz2 : 0.0;
+      const double azp = (k < g.nz || per2) ? g.idz2 : 0.0;
+      double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < 6; q++) {
-      const long o = c + nb.o[q];
-      s += nb.a[q] * (p_in[o] + (e ? (double)e[o] : 0.0) - pc);
+      for (int t = 0; t < 4; t++) s += nb.a[t] * (q(c + nb.o[t]) - qc);
+      s += azm * (qd - qc);
+      s += azp * (qu - qc);
+      const double rr = (double)rhs[c] - s;
+      r[c] = (float)rr;
+      acc += rr * rr;
+      if (e) p_out[c] = qc;
+      qd = qc;
+      qc = qu;
     }
-    const double rr = (double)rhs[c] - s;
-    r[c] = (float)rr;
-    acc += rr * rr;
-    if (e) p_out[c] = pc;
-  });
+  }
   const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const unsigned nbk = gridDim.x * gridDim.y * gridDim.z;
   double s = block_sum(acc, sh);
