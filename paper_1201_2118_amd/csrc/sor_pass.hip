@@ -130,7 +130,7 @@ constexpr int kEdge = W * 2 * kLanes;
 template <class T, int NS, int R, int W, bool ZIN>
 __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restrict__ p_out,
                                           const T* __restrict__ rhs, const Geo& g, double omega, int write,
-                                          int tile, int zc, int ntx, int nty, T* __restrict__ E, double& acc1,
+                                          int col, int z0, int z1, int ntx, T* __restrict__ E, double& acc1,
                                           double& acc2) {
   constexpr int H = 2 * NS;
   constexpr int TX = kLanes - 2 * H;
@@ -138,14 +138,10 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   constexpr int TY = ROWS - 2 * H;
   const int tx = threadIdx.x;
   const int wy = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
-  const int bx = tile % ntx;
-  const int rest = tile / ntx;
-  const int by = rest % nty;
-  const int bz = rest / nty;
+  const int bx = col % ntx;
+  const int by = col / ntx;
   const int i = bx * TX + tx - (H - 1);
   const int j0 = by * TY + wy * R - (H - 1);  // row 0 of this wave (uniform)
-  const int z0 = 1 + bz * zc;
-  const int z1 = min(g.nz, z0 + zc - 1);
   const int per0 = g.per[0], per1 = g.per[1], per2 = g.per[2];
 
   const bool ownx = tx >= H && tx < kLanes - H && i <= g.nx;
@@ -444,18 +440,38 @@ k_sor_pass(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restric
   for (int q = flat_tid(); q < 2 * NS * 2 * kEdge<W>; q += kLanes * W) E[q] = T(0);
   __syncthreads();
 
-  // Persistent loop over tiles, split into 8 contiguous ranges, one per
-  // XCD (workgroup b runs on XCD b % 8).
+  // Persistent workgroups.  Workgroup b runs on XCD b % 8; its position in
+  // XCD-major order, li, makes the work of neighbouring workgroups on one
+  // XCD neighbouring columns (same L2).
   const int G = gridDim.x;
   const bool by_xcd = G >= 8;
   const int xcd = by_xcd ? (blockIdx.x & 7) : 0;
   const int slot = by_xcd ? (blockIdx.x >> 3) : blockIdx.x;
-  const int nwg_x = by_xcd ? (G >> 3) + (xcd < (G & 7) ? 1 : 0) : G;
-  const int lo = by_xcd ? (int)((long)ntiles * xcd / 8) : 0;
-  const int hi = by_xcd ? (int)((long)ntiles * (xcd + 1) / 8) : ntiles;
-  for (int tile = lo + slot; tile < hi; tile += nwg_x) {
-    pass_tile<T, NS, R, W, ZIN>(p_in, p_out, rhs, g, omega, write, tile, zc, ntx, nty, E, acc1, acc2);
-    __syncthreads();
+  const int li = by_xcd ? xcd * (G >> 3) + min(xcd, G & 7) + slot : blockIdx.x;
+  const int ncols = ntx * nty;
+  if (zc > 0) {
+    // tiles of zc planes: column-major tile list, dealt round-robin in li order
+    for (int tile = li; tile < ntiles; tile += G) {
+      const int col = tile % ncols, bz = tile / ncols;
+      const int z0 = 1 + bz * zc;
+      pass_tile<T, NS, R, W, ZIN>(p_in, p_out, rhs, g, omega, write, col, z0, min(g.nz, z0 + zc - 1), ntx, E,
+                                  acc1, acc2);
+      __syncthreads();
+    }
+  } else {
+    // balanced: workgroup li takes an equal share of the (column, plane)
+    // space in column order, cut at column ends into z ranges
+    const long ptot = (long)ncols * g.nz;
+    long q0 = ptot * li / G;
+    const long q1 = ptot * (li + 1) / G;
+    while (q0 < q1) {
+      const int col = (int)(q0 / g.nz);
+      const int z0 = (int)(q0 - (long)col * g.nz) + 1;
+      const int z1 = (int)min((long)g.nz, (long)z0 + (q1 - q0) - 1);
+      pass_tile<T, NS, R, W, ZIN>(p_in, p_out, rhs, g, omega, write, col, z0, z1, ntx, E, acc1, acc2);
+      __syncthreads();
+      q0 += z1 - z0 + 1;
+    }
   }
   if (part == nullptr) return;
 
@@ -509,8 +525,10 @@ hipError_t launch_w(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const
   constexpr int ROWS = kRows * W;
   const int ntx = (g.nx + (kLanes - 2 * H) - 1) / (kLanes - 2 * H);
   const int nty = (g.ny + (ROWS - 2 * H) - 1) / (ROWS - 2 * H);
-  const int ntz = (g.nz + zc - 1) / zc;
-  const int ntiles = ntx * nty * ntz;
+  // zc = 0: as many workgroups as are resident (each with a balanced share),
+  // but no more than there are plane-columns
+  const long ntiles_l = zc > 0 ? (long)ntx * nty * ((g.nz + zc - 1) / zc) : (long)ntx * nty * g.nz;
+  const int ntiles = (int)(ntiles_l < (1L << 30) ? ntiles_l : (1L << 30));
   int nb = pass_resident<T, NS, W>();
   if (nb <= 0 || nb > ntiles) nb = ntiles;
   const dim3 blk(kLanes, W);
@@ -574,7 +592,8 @@ template <class T>
 hipError_t launch_sor_pass(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl,
                            double* part, double omega, int m, int itermax, int write, int zero_in, int inner,
                            int ns, const SorShape& s) {
-  const int zc = s.zc > 0 ? (s.zc < g.nz ? s.zc : g.nz) : g.nz;
+  // zc = 0: balanced z ranges over the resident workgroups
+  const int zc = s.zc > 0 ? (s.zc < g.nz ? s.zc : g.nz) : 0;
   if (ns == 1) return launch_ns<T, 1>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc, s.ty);
   if (ns == 2) return launch_ns<T, 2>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc, s.ty);
   return hipErrorInvalidValue;
