@@ -176,6 +176,13 @@ void batch_item_shape(BatchItem& it, int ty, int zc);
 // One sweep of every domain of a batch in one launch (nblocks = sum of ntiles).
 template <class T> hipError_t launch_sor_batched(hipStream_t st, const BatchItem* d_items, int nitems,
                                                 int nblocks, int ty, int m, int write, int zero_in);
+// Pass-kernel geometry of an item (rows 16 / 24 / 32, ns sweeps per pass)
+// and one batched pass: first sweep index m, pass q of every domain reads
+// p[(cur + q) & 1]; force sweeps regardless of done flags without residuals.
+void pass_item_shape(BatchItem& it, int rows, int zc, int ns);
+template <class T> hipError_t launch_pass_batched(hipStream_t st, const BatchItem* d_items, int nitems,
+                                                 int nblocks, int rows, int m, int q, int ns, int zero_in,
+                                                 int force);
 
 // Adjoint of the predictor in gather form (FP64 only): z = B^T J_Phi(u)^T mu.
 hipError_t launch_adj_fgh(hipStream_t st, const Geo& g, const double* u, const double* v,

@@ -322,9 +322,10 @@ ns_status autotune(ns_solver* s, Inst& I) {
   return NS_OK;
 }
 
-// Batch shape: time rows 4 / 8 / 12 x z chunk whole / 32 / 16 with one
-// batched sweep each over all instances (zero buffers, a scratch control
-// array that never converges), keep the fastest.
+// Batch shape: time the one-sweep rows 4 / 8 / 12 and the two-sweep pass
+// rows 16 / 24 / 32 (per sweep) x z chunk whole / 32 / 16 with one batched
+// launch each over all instances (zero buffers, a scratch control array
+// that never converges), keep the fastest.
 template <class T>
 ns_status tune_batch_run(ns_solver* s, Ctl* tctl, int ty, int zc, float* ms) {
   const int n = (int)s->in.size();
@@ -342,7 +343,8 @@ ns_status tune_batch_run(ns_solver* s, Ctl* tctl, int ty, int zc, float* ms) {
     it.cur = 0;
     it.budget = 1 << 30;
     it.inner = 0;
-    batch_item_shape(it, ty, zc);
+    if (ty >= 16) pass_item_shape(it, ty, zc, 2);
+    else batch_item_shape(it, ty, zc);
     it.first = nblocks;
     nblocks += it.ntiles;
   }
@@ -353,7 +355,10 @@ ns_status tune_batch_run(ns_solver* s, Ctl* tctl, int ty, int zc, float* ms) {
   hipError_t e = hipSuccess;
   for (int it = 0; it < 4 && e == hipSuccess; it++) {
     if (it == 1) e = hipEventRecord(a, s->stream);
-    if (e == hipSuccess) e = launch_sor_batched<T>(s->stream, s->items_d, n, nblocks, ty, 1, 1, 0);
+    // sweep index 1 (pass: 0): no residual of these launches is a stop decision
+    if (e == hipSuccess)
+      e = ty >= 16 ? launch_pass_batched<T>(s->stream, s->items_d, n, nblocks, ty, 0, 0, 2, 0, 0)
+                   : launch_sor_batched<T>(s->stream, s->items_d, n, nblocks, ty, 1, 1, 0);
   }
   if (e == hipSuccess) e = hipEventRecord(b, s->stream);
   if (e == hipSuccess) e = hipEventSynchronize(b);
@@ -361,6 +366,7 @@ ns_status tune_batch_run(ns_solver* s, Ctl* tctl, int ty, int zc, float* ms) {
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (e != hipSuccess) return fail_hip(s, "batch autotune", e);
+  if (ty >= 16) *ms *= 0.5f;  // per sweep
   return NS_OK;
 }
 
@@ -368,12 +374,15 @@ ns_status autotune_batch(ns_solver* s) {
   const int n = (int)s->in.size();
   Ctl* tctl = nullptr;
   HCK(s, dmalloc((void**)&tctl, sizeof(Ctl) * n));
-  const int rows[3] = {4, 8, 12};
+  bool pass_ok = true;
+  for (auto& I : s->in) pass_ok &= pass_grid_ok(I.g, I.esz);
+  const int rows[6] = {4, 8, 12, 16, 24, 32};
   const int zcs[3] = {0, 32, 16};
   float best = 1e30f;
   ns_status st = NS_OK;
-  for (int r = 0; r < 3 && st == NS_OK; r++)
+  for (int r = 0; r < 6 && st == NS_OK; r++)
     for (int z = 0; z < 3 && st == NS_OK; z++) {
+      if (rows[r] >= 16 && !pass_ok) continue;
       float ms = 0.f;
       st = s->in[0].mixed ? tune_batch_run<float>(s, tctl, rows[r], zcs[z], &ms)
                           : tune_batch_run<double>(s, tctl, rows[r], zcs[z], &ms);
@@ -730,11 +739,100 @@ ns_status poll_all(ns_solver* s) {
   return NS_OK;
 }
 
+// Batched solve with the two-sweep pass kernel: pass q (sweeps 2q + 1 and
+// 2q + 2) of every domain in one launch until every domain is done.  A
+// domain that stops on the iterate a pass held only in registers (odd
+// final) is swept again from that pass's input (forced one-sweep launch,
+// the same arithmetic); the accepted iterate f of a domain then sits in
+// buffer (cur + ceil(f / 2)) & 1.
+template <class T>
+ns_status run_batched_pass(ns_solver* s, int n, int max_budget, int pred, int zero_first, long long bpc,
+                           const std::vector<int>& idx_of_item, std::vector<int>& fbuf) {
+  const int rows = s->batch_ty;
+  int nblocks = 0;
+  long long cells = 0;
+  for (int q = 0; q < n; q++) {
+    BatchItem& it = s->items_h[q];
+    pass_item_shape(it, rows, s->batch_zc, 2);
+    it.first = nblocks;
+    nblocks += it.ntiles;
+    cells += (long long)it.g.nx * it.g.ny * it.g.nz;
+  }
+  HCK(s, hipMemcpyAsync(s->items_d, s->items_h, sizeof(BatchItem) * n, hipMemcpyHostToDevice, s->stream));
+  const size_t rec0 = s->recs.size();
+  int m = 0;  // sweeps launched
+  bool first = true;
+  for (;;) {
+    const int chunk = first ? std::min(std::max(pred + 2, 4), max_budget + 2) : std::max(4, pred / 4);
+    first = false;
+    for (int c = 0; c < chunk && m < max_budget + 1; c += 2) {
+      Timed t(s, NS_T_SOR, 2000000 + m + 1, bpc * cells);
+      HCK(s, launch_pass_batched<T>(s->stream, s->items_d, n, nblocks, rows, m + 1, m / 2, 2, zero_first && m == 0,
+                                    0));
+      m += 2;
+    }
+    ns_status e = poll_all(s);
+    if (e != NS_OK) return e;
+    bool all = true;
+    for (int q = 0; q < n; q++) all &= s->hctl[idx_of_item[q]].done != 0;
+    if (all) break;
+    if (m >= max_budget + 1) return fail(s, NS_E_DEVICE, "batched solve ended without a decision");
+  }
+  for (size_t q = rec0; q < s->recs.size(); q++) {
+    EvRec& rc = s->recs[q];
+    if (rc.stage != NS_T_SOR || rc.m < 2000000) continue;
+    const int mm = rc.m - 2000000;
+    long long by = 0;
+    for (int it = 0; it < n; it++) {
+      const BatchItem& bi = s->items_h[it];
+      if (s->hctl[idx_of_item[it]].final_ + 1 >= mm) by += bpc * (long long)bi.g.nx * bi.g.ny * bi.g.nz;
+    }
+    if (by == 0) rc.stage = NS_T_COUNT - 1;
+    else rc.bytes = by;
+  }
+  // re-sweep the iterates held only in registers: one forced launch per
+  // kind of input (zero or stored)
+  fbuf.resize(n);
+  for (int zin = 0; zin < 2; zin++) {
+    std::vector<BatchItem> fix;
+    long long fcells = 0;
+    int fblocks = 0;
+    for (int q = 0; q < n; q++) {
+      const int f = s->hctl[idx_of_item[q]].final_;
+      const BatchItem& bi = s->items_h[q];
+      fbuf[q] = (bi.cur + (f + 1) / 2) & 1;
+      if (!(f & 1)) continue;
+      const int pq = (f - 1) / 2;  // the pass that held iterate f
+      if ((zero_first && pq == 0) != (zin == 1)) continue;
+      BatchItem it = bi;
+      it.cur = (bi.cur + pq) & 1;
+      pass_item_shape(it, rows, s->batch_zc, 1);
+      it.first = fblocks;
+      fblocks += it.ntiles;
+      fcells += (long long)it.g.nx * it.g.ny * it.g.nz;
+      fix.push_back(it);
+    }
+    if (fix.empty()) continue;
+    if ((int)fix.size() > n) return fail(s, NS_E_DEVICE, "batch table overflow");
+    // the launch reads its table before the copy below can overwrite it
+    // (same stream), and the next use of items_d uploads a full table
+    BatchItem* hbuf = s->items_h + n;
+    std::copy(fix.begin(), fix.end(), hbuf);
+    HCK(s, hipMemcpyAsync(s->items_d + n, hbuf, sizeof(BatchItem) * fix.size(), hipMemcpyHostToDevice, s->stream));
+    Timed t(s, NS_T_SOR, 2000000, bpc * fcells);
+    HCK(s, launch_pass_batched<T>(s->stream, s->items_d + n, (int)fix.size(), fblocks, rows, 1, 0, 1, zin, 1));
+    HCK(s, hipStreamSynchronize(s->stream));
+  }
+  return NS_OK;
+}
+
 // Runs launches m = 1, 2, ... over the items in s->items_h[0..n) until every
-// item is done; bpc = algorithmic bytes per cell of one sweep.
+// item is done; bpc = algorithmic bytes per cell of one sweep; fbuf[q]
+// receives the buffer of item q's accepted iterate.
 template <class T>
 ns_status run_batched(ns_solver* s, int n, int max_budget, int pred, int zero_first, long long bpc,
-                      const std::vector<int>& idx_of_item) {
+                      const std::vector<int>& idx_of_item, std::vector<int>& fbuf) {
+  if (s->batch_ty >= 16) return run_batched_pass<T>(s, n, max_budget, pred, zero_first, bpc, idx_of_item, fbuf);
   int nblocks = 0;
   long long cells = 0;
   for (int q = 0; q < n; q++) {
@@ -776,6 +874,8 @@ ns_status run_batched(ns_solver* s, int n, int max_budget, int pred, int zero_fi
     if (by == 0) rc.stage = NS_T_COUNT - 1;  // every domain had returned on its flag
     else rc.bytes = by;
   }
+  fbuf.resize(n);
+  for (int q = 0; q < n; q++) fbuf[q] = (s->items_h[q].cur + s->hctl[idx_of_item[q]].final_) & 1;
   return NS_OK;
 }
 
@@ -805,13 +905,14 @@ ns_status solve_batched_fp64(ns_solver* s, std::vector<int>& sweeps) {
     pred = std::max(pred, I.pred);
     ids[i] = i;
   }
-  ns_status e = run_batched<double>(s, n, max_budget, pred, 0, 24, ids);
+  std::vector<int> fbuf;
+  ns_status e = run_batched<double>(s, n, max_budget, pred, 0, 24, ids, fbuf);
   if (e != NS_OK) return e;
   for (int i = 0; i < n; i++) {
     Inst& I = s->in[i];
     const int f = s->hctl[i].final_;
     sweeps[i] = f;
-    I.s.pcur = (I.s.pcur + f) & 1;
+    I.s.pcur = fbuf[i];
     I.pred = f;
   }
   return NS_OK;
@@ -846,7 +947,8 @@ ns_status solve_batched_mixed(ns_solver* s, std::vector<int>& sweeps, std::vecto
       pred = std::max(pred, I.pred);
     }
     if (ids.empty()) break;
-    e = run_batched<float>(s, (int)ids.size(), max_budget, pred, 1, 12, ids);
+    std::vector<int> fbuf;
+    e = run_batched<float>(s, (int)ids.size(), max_budget, pred, 1, 12, ids, fbuf);
     if (e != NS_OK) return e;
     for (int q = 0; q < (int)ids.size(); q++) {
       const int i = ids[q];
@@ -855,7 +957,7 @@ ns_status solve_batched_mixed(ns_solver* s, std::vector<int>& sweeps, std::vecto
       sweeps[i] += f;
       I.pred = f;
       Timed t(s, NS_T_DEFECT, 0, 40LL * I.g.nx * I.g.ny * I.g.nz);
-      HCK(s, launch_defect(s->stream, I.g, I.s.p[I.s.pcur], I.e[f & 1], I.s.p[I.s.pcur ^ 1], (const float*)I.rhs,
+      HCK(s, launch_defect(s->stream, I.g, I.s.p[I.s.pcur], I.e[fbuf[q]], I.s.p[I.s.pcur ^ 1], (const float*)I.rhs,
                            I.r, I.ctl, I.part, I.prm.eta));
       I.s.pcur ^= 1;
     }
@@ -1030,16 +1132,22 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
   // several instances of one precision: one launch per sweep for all of them
   {
     bool same = n_instances > 1;
-    for (auto& I : s->in) same &= I.mixed == s->in[0].mixed && I.prm.tile[0] >= 0 && I.prm.tile[0] <= 12;
+    for (auto& I : s->in) same &= I.mixed == s->in[0].mixed && I.prm.tile[0] >= 0;
     s->batched = same;
   }
   if (s->batched) {
-    if (hipHostMalloc((void**)&s->items_h, sizeof(BatchItem) * n_instances, hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void**)&s->items_d, sizeof(BatchItem) * n_instances) != hipSuccess)
+    // room for a full table and a table of re-sweeps behind it
+    if (hipHostMalloc((void**)&s->items_h, 2 * sizeof(BatchItem) * n_instances, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipMalloc((void**)&s->items_d, 2 * sizeof(BatchItem) * n_instances) != hipSuccess)
       return bail(NS_E_OOM, "batch table allocation failed");
     if (params[0].tile[0] > 0) {
       s->batch_ty = params[0].tile[0];
       s->batch_zc = params[0].tile[1];
+      if (s->batch_ty >= 16)
+        for (auto& I : s->in)
+          if (!pass_grid_ok(I.g, I.esz))
+            return bail(NS_E_INVALID, "tile: the two-sweep pass needs periodic axes of at least 4 cells");
     } else if (autotune_batch(s) != NS_OK) {
       return bail(NS_E_DEVICE, "batch autotune: " + s->err);
     }

@@ -423,6 +423,28 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
 // With part == nullptr the pass is forced: it runs whatever the done flag
 // says and applies no stop rule (the host uses it to materialise an
 // iterate a two-sweep pass held only in registers).
+// Stop rule after a pass with first sweep index m: sweep m reports the RMS
+// residual of iterate m - 1 (sum t1), sweep m + 1 that of iterate m (t2).
+__device__ __forceinline__ void stop_rule(Ctl* ctl, int inner, int itermax, long n, int m, int ns, double t1,
+                                          double t2) {
+  const double thr = inner ? ctl->thr_in : ctl->thr;
+  auto check = [&](int mm, double tot) -> bool {
+    const double res = sqrt(tot / (double)n);
+    if (!(mm >= 1 || itermax == 0)) return false;
+    if (inner) ctl->res_in = res; else ctl->res = res;
+    const bool fin = isfinite(res);
+    if (!(res > thr) || mm >= itermax || !fin) {
+      ctl->done = 1;
+      ctl->final_ = mm;
+      if (!fin) ctl->nonfinite = 1;
+      return true;
+    }
+    return false;
+  };
+  if (!check(m - 1, t1) && ns == 2) check(m, t2);
+  ctl->ticket = 0;
+}
+
 #ifndef NS_PASS_MINW
 #define NS_PASS_MINW 1
 #endif
@@ -482,25 +504,51 @@ k_sor_pass(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restric
   if (publish_partial(part, blockIdx.x, s1, ctl, G, &sh_last)) {
     const double t1 = sum_partials(part, G, shred);
     const double t2 = NS == 2 ? sum_partials(part + G, G, shred) : 0.0;
-    if (flat_tid() == 0) {
-      const double thr = inner ? ctl->thr_in : ctl->thr;
-      // sweep mm + 1 reports the residual of iterate mm
-      auto check = [&](int mm, double tot) -> bool {
-        const double res = sqrt(tot / (double)n);
-        if (!(mm >= 1 || itermax == 0)) return false;
-        if (inner) ctl->res_in = res; else ctl->res = res;
-        const bool fin = isfinite(res);
-        if (!(res > thr) || mm >= itermax || !fin) {
-          ctl->done = 1;
-          ctl->final_ = mm;
-          if (!fin) ctl->nonfinite = 1;
-          return true;
-        }
-        return false;
-      };
-      if (!check(m - 1, t1) && NS == 2) check(m, t2);
-      ctl->ticket = 0;
-    }
+    if (flat_tid() == 0) stop_rule(ctl, inner, itermax, n, m, NS, t1, t2);
+  }
+}
+
+// Batched pass: one launch covers a pass of every domain of a batch.
+// Workgroup b belongs to the domain whose [first, first + ntiles) range
+// holds b and sweeps one tile of it (chunks of zc planes, zc = nz for whole
+// columns); each domain has its own partial sums, ticket, stop rule, budget
+// and done flag.  Pass q of a domain reads p[(cur + q) & 1] and writes the
+// other buffer.  force: sweep regardless of the done flag, no residuals.
+template <class T, int NS, int R, int W, bool ZIN>
+__global__ void __launch_bounds__(kLanes * W)
+k_pass_batched(const BatchItem* __restrict__ items, int nitems, int m, int q, int force) {
+  __shared__ T E[2 * NS * 2 * kEdge<W>];
+  __shared__ double shred[16];
+  __shared__ int sh_last;
+  const int b = blockIdx.x;
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= b) lo = mid; else hi = mid - 1;
+  }
+  const BatchItem& it = items[lo];
+  Ctl* ctl = it.ctl;
+  if (!force && ctl->done) return;
+  for (int k = flat_tid(); k < 2 * NS * 2 * kEdge<W>; k += kLanes * W) E[k] = T(0);
+  __syncthreads();
+  const Geo g = it.g;
+  const int tile = b - it.first;
+  const int ncols = it.ntx * it.nty;
+  const int col = tile % ncols, bz = tile / ncols;
+  const int z0 = 1 + bz * it.zc;
+  const int in = (it.cur + q) & 1;
+  double acc1 = 0.0, acc2 = 0.0;
+  pass_tile<T, NS, R, W, ZIN>((const T*)it.p[in], (T*)it.p[in ^ 1], (const T*)it.rhs, g, it.omega, 1, col, z0,
+                              min(g.nz, z0 + it.zc - 1), it.ntx, E, acc1, acc2);
+  __syncthreads();
+  if (force) return;
+  const double s1 = block_sum(acc1, shred);
+  const double s2 = NS == 2 ? block_sum(acc2, shred) : 0.0;
+  if (NS == 2 && flat_tid() == 0) it.part[it.ntiles + tile] = s2;
+  if (publish_partial(it.part, tile, s1, ctl, it.ntiles, &sh_last)) {
+    const double t1 = sum_partials(it.part, it.ntiles, shred);
+    const double t2 = NS == 2 ? sum_partials(it.part + it.ntiles, it.ntiles, shred) : 0.0;
+    if (flat_tid() == 0) stop_rule(ctl, it.inner, it.budget, (long)g.nx * g.ny * g.nz, m, NS, t1, t2);
   }
 }
 
@@ -552,7 +600,50 @@ hipError_t launch_ns(hipStream_t st, const Geo& g, const T* p_in, T* p_out, cons
   return hipErrorInvalidValue;
 }
 
+template <class T, int NS, int W>
+hipError_t launch_batched_w(hipStream_t st, const BatchItem* items, int nitems, int nblocks, int m, int q,
+                            int zero_in, int force) {
+  const dim3 blk(kLanes, W);
+  if (zero_in)
+    k_pass_batched<T, NS, kRows, W, true><<<nblocks, blk, 0, st>>>(items, nitems, m, q, force);
+  else
+    k_pass_batched<T, NS, kRows, W, false><<<nblocks, blk, 0, st>>>(items, nitems, m, q, force);
+  return hipGetLastError();
+}
+
+template <class T, int NS>
+hipError_t launch_batched_ns(hipStream_t st, const BatchItem* items, int nitems, int nblocks, int rows, int m,
+                             int q, int zero_in, int force) {
+  switch (rows) {
+    case 16: return launch_batched_w<T, NS, 8>(st, items, nitems, nblocks, m, q, zero_in, force);
+    case 24: return launch_batched_w<T, NS, 12>(st, items, nitems, nblocks, m, q, zero_in, force);
+    case 32: return launch_batched_w<T, NS, 16>(st, items, nitems, nblocks, m, q, zero_in, force);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+void pass_item_shape(BatchItem& it, int rows, int zc, int ns) {
+  const int h = 2 * ns;
+  it.ntx = (it.g.nx + (kLanes - 2 * h) - 1) / (kLanes - 2 * h);
+  it.nty = (it.g.ny + (rows - 2 * h) - 1) / (rows - 2 * h);
+  it.zc = zc > 0 ? (zc < it.g.nz ? zc : it.g.nz) : it.g.nz;
+  it.ntiles = it.ntx * it.nty * ((it.g.nz + it.zc - 1) / it.zc);
+}
+
+template <class T>
+hipError_t launch_pass_batched(hipStream_t st, const BatchItem* d_items, int nitems, int nblocks, int rows, int m,
+                               int q, int ns, int zero_in, int force) {
+  if (ns == 1) return launch_batched_ns<T, 1>(st, d_items, nitems, nblocks, rows, m, q, zero_in, force);
+  if (ns == 2) return launch_batched_ns<T, 2>(st, d_items, nitems, nblocks, rows, m, q, zero_in, force);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_pass_batched<double>(hipStream_t, const BatchItem*, int, int, int, int, int, int, int,
+                                                int);
+template hipError_t launch_pass_batched<float>(hipStream_t, const BatchItem*, int, int, int, int, int, int, int,
+                                               int);
 
 bool pass_shape_ok(const SorShape& s) { return s.ty == 16 || s.ty == 24 || s.ty == 32; }
 
