@@ -45,6 +45,13 @@ namespace {
 
 constexpr int kLanes = 64;  // x positions per row (one wave)
 constexpr int kRows = 2;    // rows per lane
+#ifndef NS_PASS_RING
+#define NS_PASS_RING 4
+#endif
+// Planes per register ring (input and rhs) = steps per unrolled trip: a
+// plane is loaded kRing - 2 steps before the step that first reads it.
+constexpr int kRing = NS_PASS_RING;
+static_assert(kRing == 4 || kRing == 6, "ring of 4 or 6 planes");
 
 __device__ __forceinline__ int dpp_left(int v) {  // lane l receives lane l - 1 (0 at lane 0)
   return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
@@ -214,14 +221,14 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   };
 
 
-  // rings: slot (S + q) & 3 holds plane L - 2 + q at a step with L % 4 == S
-  // relative to Lbeg; planes L and L + 1 may still be in flight
-  T P[4][R], Q[4][R];
+  // rings: slot (S + q) % kRing holds plane L - 2 + q at a step with
+  // (L - Lbeg) % kRing == S; planes L .. L + kRing - 3 may still be in flight
+  T P[kRing][R], Q[kRing][R];
   T hC[R], hD[R];                       // rhs at L - 3, L - 4
   T X1a[R], X1b[R], Ma[R], Mb[R];       // first sweep: red at L-3, L-2; iterate at L-4, L-3
   T X2a[R], X2b[R];                     // second sweep: red at L-5, L-4
 #pragma unroll
-  for (int q = 0; q < 4; q++) {
+  for (int q = 0; q < kRing; q++) {
     const long pl = plane_of(Lbeg - 2 + q);
     const Plane bp = plane_at(p_in, pl, g.sxy);
     const Plane br = plane_at(rhs, pl, g.sxy);
@@ -249,10 +256,10 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
     constexpr int S = decltype(Sc)::value;
     constexpr int SP = S & 1;
     T(&pm2)[R] = P[S];
-    T(&pm1)[R] = P[(S + 1) & 3];
-    T(&p0)[R] = P[(S + 2) & 3];
+    T(&pm1)[R] = P[(S + 1) % kRing];
+    T(&p0)[R] = P[(S + 2) % kRing];
     T(&qm2)[R] = Q[S];
-    T(&qm1)[R] = Q[(S + 1) & 3];
+    T(&qm1)[R] = Q[(S + 1) % kRing];
 
     // the input plane's edge rows
     ebuf(0, SP)[e_top] = pm1[0];
@@ -379,8 +386,8 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
       X1a[r] = X1b[r];
       X1b[r] = X1n[r];
     }
-    // refill the dead ring slots with plane L + 2
-    const long pl = plane_of(L + 2);
+    // refill the dead ring slots with plane L + kRing - 2
+    const long pl = plane_of(L + kRing - 2);
     const Plane bp = plane_at(p_in, pl, g.sxy);
     const Plane br = plane_at(rhs, pl, g.sxy);
 #pragma unroll
@@ -390,23 +397,29 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
     }
   };
 
-  // Trips of four steps.  A trip whose stage planes all lie strictly inside
-  // the domain in z (every trip on a periodic axis) and that ends by Lend
-  // takes the constant z coefficients; the last trip stops after Lend.
+  // Trips of kRing steps.  A trip whose stage planes all lie strictly
+  // inside the domain in z (every trip on a periodic axis) and that ends by
+  // Lend takes the constant z coefficients; the last trip stops after Lend.
   const int fast_lo = per2 ? INT_MIN : 2 * NS + 2;  // first step with all stage planes >= 2
   const int fast_hi = min(per2 ? INT_MAX : g.nz, Lend);  // last such step <= nz - 1, within the chunk
   using F0 = std::integral_constant<int, 0>;
   using F1 = std::integral_constant<int, 1>;
   using F2 = std::integral_constant<int, 2>;
   using F3 = std::integral_constant<int, 3>;
+  using F4 = std::integral_constant<int, 4>;
+  using F5 = std::integral_constant<int, 5>;
   using FAST = std::true_type;
   using GEN = std::false_type;
-  for (int L = Lbeg; L <= Lend; L += 4) {
-    if (L >= fast_lo && L + 3 <= fast_hi) {
+  for (int L = Lbeg; L <= Lend; L += kRing) {
+    if (L >= fast_lo && L + kRing - 1 <= fast_hi) {
       step(F0{}, FAST{}, L);
       step(F1{}, FAST{}, L + 1);
       step(F2{}, FAST{}, L + 2);
       step(F3{}, FAST{}, L + 3);
+      if constexpr (kRing > 4) {
+        step(F4{}, FAST{}, L + 4);
+        step(F5{}, FAST{}, L + 5);
+      }
     } else {
       step(F0{}, GEN{}, L);
       if (L + 1 > Lend) break;
@@ -415,6 +428,12 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
       step(F2{}, GEN{}, L + 2);
       if (L + 3 > Lend) break;
       step(F3{}, GEN{}, L + 3);
+      if constexpr (kRing > 4) {
+        if (L + 4 > Lend) break;
+        step(F4{}, GEN{}, L + 4);
+        if (L + 5 > Lend) break;
+        step(F5{}, GEN{}, L + 5);
+      }
     }
   }
 }
