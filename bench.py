@@ -82,6 +82,28 @@ def measure(prm, steps, warmup):
     }
 
 
+def copy_bandwidth(gib=2.0, reps=5):
+    """Device-to-device copy rate (read + write bytes / time) of a plain
+    torch copy on this GPU: the practical HBM ceiling the sweep is set
+    against, beside the 8 TB/s specification."""
+    import torch
+
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    secs = e0.elapsed_time(e1) * 1e-3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 * reps / secs / 1e9
+
+
 def measure_batched(steps):
     """The batched workload: 64 cavities (sizes U{24..96}, Re U[50, 1000],
     seed 4), adaptive dt (tau 0.5), FP32-mixed, one handle; one launch per
@@ -241,6 +263,7 @@ def main():
             "bytes_per_launch": dom["sor_bytes_per_launch"], "avg_launch_ms": round(dom["sor_avg_ms"], 5),
             "sweep_equivalent_gbs": round(per_launch * dom["sor_gbs"], 1),
             "tile": dom["tile"]}
+    roof["copy_gbs_measured"] = round(copy_bandwidth(), 1)
     out = {
         "metric": METRIC,
         "value": round(head["mcells"], 2),
