@@ -241,7 +241,9 @@ def main():
         log(f"{form}: {args.n}^3, warmup {args.warmup}, steps {args.steps}")
         cfg = dict(prm, precision=form)
         if args.tile:
-            cfg["tile"] = tuple(args.tile)
+            # FP64 two-sweep tiles have 16 rows
+            rows = args.tile[0] if form == "mixed" or args.tile[0] <= 16 else 16
+            cfg["tile"] = (rows, args.tile[1])
         r = measure(cfg, args.steps, args.warmup)
         st = r["stats"]
         sweeps = st["sweeps_total"] / max(st["steps"], 1)

@@ -99,9 +99,10 @@ typedef struct {
   int32_t flags;          /* NS_ALLOW_UNSTABLE | NS_TIMING */
   int32_t tile[2];        /* SOR sweep shape: {rows, z planes per chunk (0 = whole column)}.
                              rows 4, 8 or 12: one sweep per launch, that many interior rows
-                             per workgroup; rows 16, 24 or 32: two sweeps per launch
-                             (temporal blocking), that many rows per workgroup including a
-                             4-row halo on each side (periodic axes need >= 4 cells);
+                             per workgroup; rows 16, 24 or 32 (NS_FP64: 16 only): two
+                             sweeps per launch (temporal blocking), that many rows per
+                             workgroup including a 4-row halo on each side (periodic axes
+                             need >= 4 cells);
                              {0, 0} = chosen by the autotuner; rows = -1 selects the unfused
                              one-pass-per-colour sweeps (reference path). The fused shapes
                              address a plane with 31-bit byte offsets: larger planes need

@@ -37,8 +37,11 @@ struct Ctl {
   int32_t nonfinite;
   int32_t outer_done;  // mixed: outer residual met the tolerance
   uint32_t ticket;     // last-workgroup counter of reductions (reset by the last group)
-  int32_t pad_[3];
+  int32_t pad_[9];     // one 128-byte cache line per control block: kernels of different
+                       // instances run concurrently on different XCDs, whose L2s are not
+                       // coherent with each other, and must not share a line
 };
+static_assert(sizeof(Ctl) == 128, "control block is one 128-byte line");
 
 // Tunables of the red-black sweep (chosen per grid by the autotuner).
 // ty = 4 / 8 / 12: fused one-sweep kernel with ty interior rows per
@@ -149,6 +152,7 @@ template <class T> hipError_t launch_sor_pass(hipStream_t st, const Geo& g, cons
                                              int itermax, int write, int zero_in, int inner, int ns,
                                              const SorShape& shape);
 bool pass_shape_ok(const SorShape& s);
+bool pass_rows_ok(int rows, bool f32);  // FP64: 16 rows only; FP32: 16, 24 or 32
 bool pass_grid_ok(const Geo& g, size_t esz);  // periodic axes >= 4 cells, plane offsets in 31 bits
 int pass_max_partials(const Geo& g);
 int pass_resident_groups(int ty, bool f32, int ns);

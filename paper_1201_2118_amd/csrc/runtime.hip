@@ -94,6 +94,13 @@ struct ns_solver {
   int batch_ty = 8, batch_zc = 0;
   BatchItem* items_h = nullptr;  // pinned
   BatchItem* items_d = nullptr;
+  // batched: the per-domain stages (boundary fill, predictor, rhs, defect,
+  // projection) are spread over a few library streams so that the small
+  // kernels of different domains overlap
+  static constexpr int kAux = 4;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kAux] = {};
 };
 
 namespace {
@@ -195,6 +202,8 @@ ns_status validate(const ns_params& p, int idx) {
   if (p.tile[1] < 0) return bad("tile[1] must be >= 0");
   if (p.tile[0] > 0 && (double)(p.nx + 2) * (p.ny + 2) * (p.precision == NS_MIXED ? 4 : 8) >= 2147483648.0)
     return bad("planes this large need the unfused sweeps (tile = {-1, 0})");
+  if (p.tile[0] > 16 && p.precision == NS_FP64)
+    return bad("FP64 two-sweep tiles have 16 rows (tile[0] = 16)");
   if (p.tile[0] >= 16)
     for (int a = 0; a < 3; a++)
       if (p.bc[a] == NS_BC_PERIODIC && n[a] < 4) return bad("the two-sweep pass needs periodic axes of at least 4 cells");
@@ -294,7 +303,7 @@ ns_status autotune(ns_solver* s, Inst& I) {
   ns_status st = NS_OK;
   for (int r = 0; r < 6 && st == NS_OK; r++) {
     const bool pass = rows[r] >= 16;
-    if (pass && !pass_ok) continue;
+    if (pass && (!pass_ok || !pass_rows_ok(rows[r], I.mixed))) continue;
     std::vector<int> zcs = {0, 32, 64, 128};
     const int res = pass ? pass_resident_groups(rows[r], I.mixed, 2) : fused_resident(rows[r], I.mixed);
     const int cols = pass ? pass_columns(I.g, rows[r], 2) : fused_columns(I.g, rows[r]);
@@ -382,7 +391,7 @@ ns_status autotune_batch(ns_solver* s) {
   ns_status st = NS_OK;
   for (int r = 0; r < 6 && st == NS_OK; r++)
     for (int z = 0; z < 3 && st == NS_OK; z++) {
-      if (rows[r] >= 16 && !pass_ok) continue;
+      if (rows[r] >= 16 && (!pass_ok || !pass_rows_ok(rows[r], s->in[0].mixed))) continue;
       float ms = 0.f;
       st = s->in[0].mixed ? tune_batch_run<float>(s, tctl, rows[r], zcs[z], &ms)
                           : tune_batch_run<double>(s, tctl, rows[r], zcs[z], &ms);
@@ -729,6 +738,44 @@ ns_status step_inst(ns_solver* s, int idx, State& S, bool account) {
   return e;
 }
 
+// Runs f(i) for the domains i of `ids` with the work of the q-th on library
+// stream q % kAux, ordered after everything queued so far on the handle's
+// stream, which then waits for all of it.  keep_going: run every domain and
+// return the first error, else stop at the first error.
+template <class F>
+ns_status fan_out(ns_solver* s, const std::vector<int>& ids, bool keep_going, F&& f) {
+  ns_status ret = NS_OK;
+  if (!s->aux[0]) {
+    for (int i : ids) {
+      const ns_status e = f(i);
+      if (e != NS_OK && ret == NS_OK) ret = e;
+      if (ret != NS_OK && !keep_going) return ret;
+    }
+    return ret;
+  }
+  hipStream_t main = s->stream;
+  HCK(s, hipEventRecord(s->ev_fork, main));
+  for (int k = 0; k < ns_solver::kAux; k++) HCK(s, hipStreamWaitEvent(s->aux[k], s->ev_fork, 0));
+  for (size_t q = 0; q < ids.size(); q++) {
+    s->stream = s->aux[q % ns_solver::kAux];
+    const ns_status e = f(ids[q]);
+    if (e != NS_OK && ret == NS_OK) ret = e;
+    if (ret != NS_OK && !keep_going) break;
+  }
+  s->stream = main;
+  for (int k = 0; k < ns_solver::kAux; k++) {
+    HCK(s, hipEventRecord(s->ev_join[k], s->aux[k]));
+    HCK(s, hipStreamWaitEvent(main, s->ev_join[k], 0));
+  }
+  return ret;
+}
+
+std::vector<int> all_ids(int n) {
+  std::vector<int> v(n);
+  for (int i = 0; i < n; i++) v[i] = i;
+  return v;
+}
+
 // ---- batched solves ------------------------------------------------------------
 // Every domain of the handle is swept by one launch per sweep
 // (launch_sor_batched); each domain keeps its own stop rule, budget and done
@@ -923,13 +970,17 @@ ns_status solve_batched_mixed(ns_solver* s, std::vector<int>& sweeps, std::vecto
   const long long big = 1;
   (void)big;
   for (int i = 0; i < n; i++) {
-    Inst& I = s->in[i];
     sweeps[i] = 0;
     outer[i] = 0;
+  }
+  ns_status e0 = fan_out(s, all_ids(n), false, [&](int i) {
+    Inst& I = s->in[i];
     Timed t(s, NS_T_DEFECT, 0, 20LL * I.g.nx * I.g.ny * I.g.nz);
     HCK(s, launch_defect(s->stream, I.g, I.s.p[I.s.pcur], nullptr, nullptr, (const float*)I.rhs, I.r, I.ctl,
                          I.part, I.prm.eta));
-  }
+    return NS_OK;
+  });
+  if (e0 != NS_OK) return e0;
   for (;;) {
     ns_status e = poll_all(s);
     if (e != NS_OK) return e;
@@ -950,17 +1001,20 @@ ns_status solve_batched_mixed(ns_solver* s, std::vector<int>& sweeps, std::vecto
     std::vector<int> fbuf;
     e = run_batched<float>(s, (int)ids.size(), max_budget, pred, 1, 12, ids, fbuf);
     if (e != NS_OK) return e;
-    for (int q = 0; q < (int)ids.size(); q++) {
-      const int i = ids[q];
+    std::vector<int> fb_of(n, 0);
+    for (int q = 0; q < (int)ids.size(); q++) fb_of[ids[q]] = fbuf[q];
+    e = fan_out(s, ids, false, [&](int i) {
       Inst& I = s->in[i];
       const int f = s->hctl[i].final_;
       sweeps[i] += f;
       I.pred = f;
       Timed t(s, NS_T_DEFECT, 0, 40LL * I.g.nx * I.g.ny * I.g.nz);
-      HCK(s, launch_defect(s->stream, I.g, I.s.p[I.s.pcur], I.e[fbuf[q]], I.s.p[I.s.pcur ^ 1], (const float*)I.rhs,
-                           I.r, I.ctl, I.part, I.prm.eta));
+      HCK(s, launch_defect(s->stream, I.g, I.s.p[I.s.pcur], I.e[fb_of[i]], I.s.p[I.s.pcur ^ 1],
+                           (const float*)I.rhs, I.r, I.ctl, I.part, I.prm.eta));
       I.s.pcur ^= 1;
-    }
+      return NS_OK;
+    });
+    if (e != NS_OK) return e;
   }
   return NS_OK;
 }
@@ -968,18 +1022,15 @@ ns_status solve_batched_mixed(ns_solver* s, std::vector<int>& sweeps, std::vecto
 template <class T>
 ns_status step_batched(ns_solver* s) {
   const int n = (int)s->in.size();
-  for (int i = 0; i < n; i++) {
-    ns_status e = step_pre<T>(s, i, s->in[i].s);
-    if (e != NS_OK) return e;
-  }
-  std::vector<int> sweeps(n, 0), outer(n, 0);
-  ns_status e = s->in[0].mixed ? solve_batched_mixed(s, sweeps, outer) : solve_batched_fp64(s, sweeps);
+  const std::vector<int> ids = all_ids(n);
+  ns_status e = fan_out(s, ids, false, [&](int i) { return step_pre<T>(s, i, s->in[i].s); });
   if (e != NS_OK) return e;
-  ns_status ret = NS_OK;
-  for (int i = 0; i < n; i++) {
-    e = step_post<T>(s, i, s->in[i].s, sweeps[i], outer[i], true);
-    if (e != NS_OK && ret == NS_OK) ret = e;
-  }
+  std::vector<int> sweeps(n, 0), outer(n, 0);
+  e = s->in[0].mixed ? solve_batched_mixed(s, sweeps, outer) : solve_batched_fp64(s, sweeps);
+  if (e != NS_OK) return e;
+  const ns_status ret = fan_out(s, ids, true, [&](int i) {
+    return step_post<T>(s, i, s->in[i].s, sweeps[i], outer[i], true);
+  });
   if (s->timing) {
     HCK(s, hipStreamSynchronize(s->stream));
     harvest(s, 1 << 30);
@@ -1136,6 +1187,12 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
     s->batched = same;
   }
   if (s->batched) {
+    for (int k = 0; k < ns_solver::kAux; k++)
+      if (hipStreamCreateWithFlags(&s->aux[k], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&s->ev_join[k], hipEventDisableTiming) != hipSuccess)
+        return bail(NS_E_DEVICE, "stream creation failed");
+    if (hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess)
+      return bail(NS_E_DEVICE, "event creation failed");
     // room for a full table and a table of re-sweeps behind it
     if (hipHostMalloc((void**)&s->items_h, 2 * sizeof(BatchItem) * n_instances, hipHostMallocDefault) !=
             hipSuccess ||
@@ -1385,6 +1442,11 @@ void ns_destroy(ns_solver* s) {
   if (s->hctl) (void)hipHostFree(s->hctl);
   if (s->items_h) (void)hipHostFree(s->items_h);
   (void)hipFree(s->items_d);
+  for (int k = 0; k < ns_solver::kAux; k++) {
+    if (s->aux[k]) (void)hipStreamDestroy(s->aux[k]);
+    if (s->ev_join[k]) (void)hipEventDestroy(s->ev_join[k]);
+  }
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
   (void)hipFree(s->ctl_all);
   (void)hipFree(s->stage);
   delete s;

@@ -608,13 +608,23 @@ hipError_t launch_w(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const
   return hipGetLastError();
 }
 
+// FP64 tiles have 16 rows: with 12 or 16 waves the FP64 state of two rows per
+// lane does not fit the registers of the occupancy those workgroups need.
+template <class T>
+constexpr bool rows_ok(int rows) {
+  return rows == 16 || (sizeof(T) == 4 && (rows == 24 || rows == 32));
+}
+
 template <class T, int NS>
 hipError_t launch_ns(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl, double* part,
                      double omega, int m, int itermax, int write, int zero_in, int inner, int zc, int rows) {
-  switch (rows) {
-    case 16: return launch_w<T, NS, 8>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
-    case 24: return launch_w<T, NS, 12>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
-    case 32: return launch_w<T, NS, 16>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+  if (rows == 16)
+    return launch_w<T, NS, 8>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+  if constexpr (sizeof(T) == 4) {
+    if (rows == 24)
+      return launch_w<T, NS, 12>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+    if (rows == 32)
+      return launch_w<T, NS, 16>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
   }
   return hipErrorInvalidValue;
 }
@@ -633,10 +643,10 @@ hipError_t launch_batched_w(hipStream_t st, const BatchItem* items, int nitems, 
 template <class T, int NS>
 hipError_t launch_batched_ns(hipStream_t st, const BatchItem* items, int nitems, int nblocks, int rows, int m,
                              int q, int zero_in, int force) {
-  switch (rows) {
-    case 16: return launch_batched_w<T, NS, 8>(st, items, nitems, nblocks, m, q, zero_in, force);
-    case 24: return launch_batched_w<T, NS, 12>(st, items, nitems, nblocks, m, q, zero_in, force);
-    case 32: return launch_batched_w<T, NS, 16>(st, items, nitems, nblocks, m, q, zero_in, force);
+  if (rows == 16) return launch_batched_w<T, NS, 8>(st, items, nitems, nblocks, m, q, zero_in, force);
+  if constexpr (sizeof(T) == 4) {
+    if (rows == 24) return launch_batched_w<T, NS, 12>(st, items, nitems, nblocks, m, q, zero_in, force);
+    if (rows == 32) return launch_batched_w<T, NS, 16>(st, items, nitems, nblocks, m, q, zero_in, force);
   }
   return hipErrorInvalidValue;
 }
@@ -682,16 +692,16 @@ int pass_max_partials(const Geo& g) {
 }
 
 int pass_resident_groups(int ty, bool f32, int ns) {
-  switch (ty) {
-    case 16: return ns == 1 ? (f32 ? pass_resident<float, 1, 8>() : pass_resident<double, 1, 8>())
-                            : (f32 ? pass_resident<float, 2, 8>() : pass_resident<double, 2, 8>());
-    case 24: return ns == 1 ? (f32 ? pass_resident<float, 1, 12>() : pass_resident<double, 1, 12>())
-                            : (f32 ? pass_resident<float, 2, 12>() : pass_resident<double, 2, 12>());
-    case 32: return ns == 1 ? (f32 ? pass_resident<float, 1, 16>() : pass_resident<double, 1, 16>())
-                            : (f32 ? pass_resident<float, 2, 16>() : pass_resident<double, 2, 16>());
-  }
+  if (ty == 16)
+    return ns == 1 ? (f32 ? pass_resident<float, 1, 8>() : pass_resident<double, 1, 8>())
+                   : (f32 ? pass_resident<float, 2, 8>() : pass_resident<double, 2, 8>());
+  if (!f32) return 0;  // FP64 tiles have 16 rows
+  if (ty == 24) return ns == 1 ? pass_resident<float, 1, 12>() : pass_resident<float, 2, 12>();
+  if (ty == 32) return ns == 1 ? pass_resident<float, 1, 16>() : pass_resident<float, 2, 16>();
   return 0;
 }
+
+bool pass_rows_ok(int rows, bool f32) { return f32 ? rows_ok<float>(rows) : rows_ok<double>(rows); }
 
 int pass_columns(const Geo& g, int ty, int ns) {
   const int h = 2 * ns;

@@ -78,6 +78,7 @@ def _create(prm, flags=0, edit=None):
     (lambda p: setattr(p, "struct_size", 8), "struct_size"),
     (lambda p: setattr(p, "tol", float("nan")), "tol"),
     (lambda p: p.tile.__setitem__(0, 20), "tile[0]"),
+    (lambda p: p.tile.__setitem__(0, 24), "16 rows"),
     (lambda p: (p.tile.__setitem__(0, 16), p.bc.__setitem__(2, 1), setattr(p, "nz", 2)), "at least 4 cells"),
     (lambda p: (p.tile.__setitem__(0, 8), setattr(p, "nx", 24000), setattr(p, "ny", 24000), setattr(p, "nz", 2)),
      "unfused"),
