@@ -171,12 +171,15 @@ def traffic_from_profile(kernel_tag, tile):
         return None
 
 
-def step_bytes(n, sweeps, mixed, outers=1):
-    """Algorithmic HBM bytes of one step per cell (minimum single pass per
-    stage): FP64 112 + 24 S; mixed 60 + 12 S + 28 O."""
+def step_bytes(n, sweeps, mixed, outers=1, per_launch=1):
+    """Algorithmic HBM bytes of one step (minimum single pass per launch):
+    FP64 112 + 24 L, mixed 60 + 12 L + 28 O per cell, with L = S / k sweep
+    launches for S sweeps done k per launch (k = 1 gives the one-sweep model
+    of 112 + 24 S and 60 + 12 S + 28 O)."""
+    launches = -(-sweeps // per_launch)
     if mixed:
-        return n * (60 + 12 * sweeps + 28 * outers)
-    return n * (112 + 24 * sweeps)
+        return n * (60 + 12 * launches + 28 * outers)
+    return n * (112 + 24 * launches)
 
 
 def cpu_baseline(prm):
@@ -247,7 +250,10 @@ def main():
         r = measure(cfg, args.steps, args.warmup)
         st = r["stats"]
         sweeps = st["sweeps_total"] / max(st["steps"], 1)
-        r["alg_gbs"] = step_bytes(n, sweeps, form == "mixed", max(st["outer_max"], 1)) / (r["ms_per_step"] * 1e-3) / 1e9
+        k = 2 if r["tile"][0] >= 16 else 1
+        o = max(st["outer_max"], 1)
+        r["alg_gbs"] = step_bytes(n, sweeps, form == "mixed", o, k) / (r["ms_per_step"] * 1e-3) / 1e9
+        r["one_sweep_gbs"] = step_bytes(n, sweeps, form == "mixed", o, 1) / (r["ms_per_step"] * 1e-3) / 1e9
         log(f"{form}: {r['mcells']:.1f} Mcell-steps/s, {r['ms_per_step']:.1f} ms/step, "
             f"sor {r['sor_avg_ms']:.3f} ms/launch = {r['sor_gbs']:.0f} GB/s")
         res[form] = r
@@ -264,6 +270,7 @@ def main():
             "sweeps_per_launch": per_launch,
             "bytes_per_launch": dom["sor_bytes_per_launch"], "avg_launch_ms": round(dom["sor_avg_ms"], 5),
             "sweep_equivalent_gbs": round(per_launch * dom["sor_gbs"], 1),
+            "limiter": "vector-ALU issue (two sweeps per launch; see the design notes)" if per_launch == 2 else "HBM",
             "tile": dom["tile"]}
     roof["copy_gbs_measured"] = round(copy_bandwidth(), 1)
     out = {
@@ -283,6 +290,7 @@ def main():
                    "gamma": prm["gamma"], "omega": prm["omega"], "tol": prm["tol"],
                    "itermax": prm["itermax"], "precision": "mixed" if head is res.get("mixed") else "fp64"},
         "hbm_gbs_algorithmic": round(head["alg_gbs"], 1),
+        "gbs_one_sweep_model": round(head["one_sweep_gbs"], 1),
         "sweeps_per_step": head["stats"]["sweeps_total"] / max(head["stats"]["steps"], 1),
         "stage_ms": {k: round(v, 4) for k, v in head["stage_ms"].items()},
         "roofline": roof,
@@ -290,7 +298,8 @@ def main():
     if "fp64" in res and head is not res["fp64"]:
         f = res["fp64"]
         out["fp64"] = {"value": round(f["mcells"], 2), "ms_per_step": round(f["ms_per_step"], 3),
-                       "hbm_gbs_algorithmic": round(f["alg_gbs"], 1), "sor_gbs": round(f["sor_gbs"], 1),
+                       "hbm_gbs_algorithmic": round(f["alg_gbs"], 1),
+                       "gbs_one_sweep_model": round(f["one_sweep_gbs"], 1), "sor_gbs": round(f["sor_gbs"], 1),
                        "sor_avg_ms": round(f["sor_avg_ms"], 5), "tile": f["tile"],
                        "stage_ms": {k: round(v, 4) for k, v in f["stage_ms"].items()}}
     if args.batched_steps > 0:
