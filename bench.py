@@ -228,8 +228,8 @@ def main():
                          "known size that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the domain would be "
-              "split into z slabs with halo exchange; see the design notes). Run with --gpus 1.",
+        print("bench.py measures one GPU: there is no multi-GPU path (the domain would be "
+              "split into z slabs with halo exchange). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -270,7 +270,7 @@ def main():
             "sweeps_per_launch": per_launch,
             "bytes_per_launch": dom["sor_bytes_per_launch"], "avg_launch_ms": round(dom["sor_avg_ms"], 5),
             "sweep_equivalent_gbs": round(per_launch * dom["sor_gbs"], 1),
-            "limiter": "vector-ALU issue (two sweeps per launch; see the design notes)" if per_launch == 2 else "HBM",
+            "limiter": "vector-ALU issue (two sweeps per launch)" if per_launch == 2 else "HBM",
             "tile": dom["tile"]}
     roof["copy_gbs_measured"] = round(copy_bandwidth(), 1)
     out = {

@@ -13,7 +13,7 @@
  * staggered grid in the Hirt / NASA-VOF2D lineage, evaluated as stencils
  * ("Background and Governing Equations", the paragraph after eq. (1)).  The
  * paper prints no stencil, integrator or solver, so every discrete choice
- * below is the reading recorded in the design notes: the MAC arrangement,
+ * below is a reading of the paper, stated where it is implemented: the MAC arrangement,
  * the donor-cell-blended conservative momentum predictor (F, G, H), the
  * pressure-Poisson right-hand side, red-black SOR on the boundary-eliminated
  * Neumann Laplacian with an RMS residual stop rule, and the velocity

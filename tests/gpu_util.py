@@ -11,7 +11,7 @@ def masks(prm):
 
 
 def rel(a, b, m):
-    """max |a - b| / max |b| over the mask (A10 of the design notes)."""
+    """max |a - b| / max |b| over the mask."""
     den = np.abs(b[m]).max()
     return float(np.abs(a[m] - b[m]).max() / (den if den > 0 else 1.0))
 
