@@ -45,13 +45,14 @@ namespace {
 
 constexpr int kLanes = 64;  // x positions per row (one wave)
 constexpr int kRows = 2;    // rows per lane
-#ifndef NS_PASS_RING
-#define NS_PASS_RING 4
-#endif
 // Planes per register ring (input and rhs) = steps per unrolled trip: a
-// plane is loaded kRing - 2 steps before the step that first reads it.
-constexpr int kRing = NS_PASS_RING;
-static_assert(kRing == 4 || kRing == 6, "ring of 4 or 6 planes");
+// plane is loaded ring - 2 steps before the step that first reads it.  Six
+// planes (loads four steps ahead) where the registers allow it at the
+// workgroup's occupancy: FP32 with 12 waves; four elsewhere.
+template <class T, int W>
+constexpr int ring_of() {
+  return sizeof(T) == 4 && W == 12 ? 6 : 4;
+}
 
 __device__ __forceinline__ int dpp_left(int v) {  // lane l receives lane l - 1 (0 at lane 0)
   return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
@@ -142,6 +143,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   constexpr int H = 2 * NS;
   constexpr int TX = kLanes - 2 * H;
   constexpr int ROWS = R * W;
+  constexpr int kRing = ring_of<T, W>();
   constexpr int TY = ROWS - 2 * H;
   const int tx = threadIdx.x;
   const int wy = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
