@@ -394,7 +394,7 @@ template <class T>
 hipError_t launch_fgh(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, const T* fx,
                       const T* fy, const T* fz, T* F, T* G, T* H, const Ctl* ctl, double re,
                       double gamma, const double gf[3]) {
-  k_fgh<T><<<cell_grid(g, false), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, false), u, v, w, fx, fy, fz, F, G, H, g, ctl, 1.0 / re,
+  k_fgh<T><<<cell_grid(g, 0), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, 0), u, v, w, fx, fy, fz, F, G, H, g, ctl, 1.0 / re,
                                                      gamma, gf[0], gf[1], gf[2]);
   return hipGetLastError();
 }
@@ -402,7 +402,8 @@ hipError_t launch_fgh(hipStream_t st, const Geo& g, const T* u, const T* v, cons
 size_t reduce_blocks(const Geo& g) {
   long n = (long)g.nx * g.ny * g.nz;
   size_t m = (size_t)grid_for(n);
-  if ((size_t)cell_blocks(g, true) > m) m = cell_blocks(g, true);
+  if ((size_t)cell_blocks(g, kRedRhs) > m) m = cell_blocks(g, kRedRhs);
+  if ((size_t)cell_blocks(g, kRedDefect) > m) m = cell_blocks(g, kRedDefect);
   // the fused sweep has the most workgroups with 4 rows and 1-plane chunks
   const size_t f = (size_t)fused_num_blocks(g, SorShape{4, 1});
   if (f > m) m = f;
@@ -413,14 +414,14 @@ size_t reduce_blocks(const Geo& g) {
 template <class T>
 hipError_t launch_rhs(hipStream_t st, const Geo& g, const T* F, const T* G, const T* H, T* rhs,
                       Ctl* ctl, double* part, double tol, double unit_dt) {
-  k_rhs<T><<<cell_grid(g, true), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, true), F, G, H, rhs, g, ctl, part, tol, unit_dt != 0.0);
+  k_rhs<T><<<cell_grid(g, kRedRhs), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, kRedRhs), F, G, H, rhs, g, ctl, part, tol, unit_dt != 0.0);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_project(hipStream_t st, const Geo& g, const T* F, const T* G, const T* H,
                           const double* p, T* u, T* v, T* w, const Ctl* ctl, double unit_dt) {
-  k_project<T><<<cell_grid(g, false), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, false), F, G, H, p, u, v, w, g, ctl, unit_dt != 0.0);
+  k_project<T><<<cell_grid(g, 0), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, 0), F, G, H, p, u, v, w, g, ctl, unit_dt != 0.0);
   return hipGetLastError();
 }
 
@@ -430,13 +431,13 @@ hipError_t launch_umax(hipStream_t st, const Geo& g, const T* u, const T* v, con
   double wm[3] = {0, 0, 0};
   for (int f = 0; f < 6; f++)
     for (int c = 0; c < 3; c++) wm[c] = fmax(wm[c], fabs(wall[f][c]));
-  k_umax<T><<<cell_grid(g, true), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, true), u, v, w, g, ctl, part, re, tau, wm[0], wm[1], wm[2]);
+  k_umax<T><<<cell_grid(g, kRedRhs), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, kRedRhs), u, v, w, g, ctl, part, re, tau, wm[0], wm[1], wm[2]);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_divergence(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, T* out) {
-  k_divergence<T><<<cell_grid(g, false), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, false), u, v, w, out, g);
+  k_divergence<T><<<cell_grid(g, 0), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, 0), u, v, w, out, g);
   return hipGetLastError();
 }
 

@@ -97,27 +97,28 @@ size_t reduce_blocks(const Geo& g);  // partial-sum slots any reduction may need
 // workgroups of one (x, y) tile split z into runs of consecutive planes.
 // Consecutive lanes take consecutive x, so a wave reads 64 contiguous values
 // per row.  Kernels without a reduction take short runs (many workgroups);
-// kernels with one take runs long enough to keep the partial sums that the
-// last workgroup adds up to a few thousand.
+// kernels with one take runs long enough that about `target` workgroups
+// remain, whose partial sums the last workgroup adds up (measured at 512^3:
+// 1024 for the rhs and the time step, 2048 for the defect).
 #ifndef NS_CELL_Z
 #define NS_CELL_Z 4  // planes per workgroup, kernels without a reduction
 #endif
 constexpr int kCellX = 64, kCellY = 4;
-constexpr long kCellRedBlocks = 4096;  // target workgroups of a reducing cell kernel
-inline int cell_zrun(const Geo& g, bool reducing) {
+constexpr long kRedRhs = 1024, kRedDefect = 2048;
+inline int cell_zrun(const Geo& g, long target) {
   const long cols = (long)((g.nx + kCellX - 1) / kCellX) * ((g.ny + kCellY - 1) / kCellY);
   long z = NS_CELL_Z;
-  if (reducing) {
-    const long want = (cols * g.nz + kCellRedBlocks - 1) / kCellRedBlocks;
+  if (target > 0) {
+    const long want = (cols * g.nz + target - 1) / target;
     if (want > z) z = want;
   }
   const long minz = (g.nz + 65534) / 65535;  // grid z limit
   if (z < minz) z = minz;
   return (int)(z < g.nz ? z : g.nz);
 }
-inline dim3 cell_grid(const Geo& g, bool reducing) {
+inline dim3 cell_grid(const Geo& g, long target) {
   const int bx = (g.nx + kCellX - 1) / kCellX, by = (g.ny + kCellY - 1) / kCellY;
-  const int zr = cell_zrun(g, reducing);
+  const int zr = cell_zrun(g, target);
   return dim3(bx, by, (g.nz + zr - 1) / zr);
 }
 // f(i, j, k, c) for every interior cell of this workgroup's (x, y) tile and
@@ -132,8 +133,8 @@ __device__ __forceinline__ void for_cells(const Geo& g, int zr, F&& f) {
   long c = (long)k0 * g.sxy + (long)j * g.sx + i;
   for (int k = k0; k <= k1; k++, c += g.sxy) f(i, j, k, c);
 }
-inline unsigned cell_blocks(const Geo& g, bool reducing) {
-  const dim3 d = cell_grid(g, reducing);
+inline unsigned cell_blocks(const Geo& g, long target) {
+  const dim3 d = cell_grid(g, target);
   return d.x * d.y * d.z;
 }
 int sor_num_blocks(const Geo& g, const SorShape& s);

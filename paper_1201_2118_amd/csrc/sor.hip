@@ -230,7 +230,7 @@ hipError_t launch_defect(hipStream_t st, const Geo& g, const double* p_in, const
                          double* p_out, const float* rhs, float* r, Ctl* ctl, double* part,
                          double eta) {
   const long n = (long)g.nx * g.ny * g.nz;
-  k_defect<<<cell_grid(g, true), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, true), p_in, e, p_out, rhs, r, g, ctl, part, eta);
+  k_defect<<<cell_grid(g, kRedDefect), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, kRedDefect), p_in, e, p_out, rhs, r, g, ctl, part, eta);
   return hipGetLastError();
 }
 
