@@ -44,14 +44,16 @@ namespace ns {
 namespace {
 
 constexpr int kLanes = 64;  // x positions per row (one wave)
-constexpr int kRows = 2;    // rows per lane
+// Rows per lane of the 24- and 32-row tiles (the 16-row tile has 2 rows on
+// 8 waves); waves = rows / rows per lane.
+constexpr int kR24 = 2, kR32 = 2;  // 3 rows on 8 waves and 4 rows on 8 waves ran slower at 512^3
 // Planes per register ring (input and rhs) = steps per unrolled trip: a
 // plane is loaded ring - 2 steps before the step that first reads it.  Six
 // planes (loads four steps ahead) where the registers allow it at the
 // workgroup's occupancy: FP32 with 12 waves; four elsewhere.
-template <class T, int W>
+template <class T, int R, int W>
 constexpr int ring_of() {
-  return sizeof(T) == 4 && W == 12 ? 6 : 4;
+  return sizeof(T) == 4 && W == 12 && R == 2 ? 6 : 4;
 }
 
 __device__ __forceinline__ int dpp_left(int v) {  // lane l receives lane l - 1 (0 at lane 0)
@@ -89,18 +91,48 @@ __device__ __forceinline__ int wrap_clamp(int i, int n, int per) {
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// sum_nb a_nb p_nb - diag p_c, one rounding sequence.
+// sum_nb a_nb p_nb - diag p_c, one rounding sequence; the x neighbours
+// are lane l - 1's and lane l + 1's pc.
 template <class T>
-__device__ __forceinline__ T stencil(T pc, T pw, T pe, T ps, T pn, T pd, T pu, T axm, T axp, T aym, T ayp,
-                                     T azm, T azp, T diag) {
-  T t = pw * axm;
-  t = fmaT(pe, axp, t);
+__device__ __forceinline__ T stencil_chain(T t, T ps, T pn, T pd, T pu, T pc, T aym, T ayp, T azm, T azp,
+                                           T diag) {
   t = fmaT(aym, ps, t);
   t = fmaT(ayp, pn, t);
   t = fmaT(azm, pd, t);
   t = fmaT(azp, pu, t);
   return fmaT(-diag, pc, t);
 }
+__device__ __forceinline__ double stencil(double pc, double ps, double pn, double pd, double pu, double axm,
+                                          double axp, double aym, double ayp, double azm, double azp,
+                                          double diag) {
+  double t = from_left(pc) * axm;
+  t = fmaT(from_right(pc), axp, t);
+  return stencil_chain(t, ps, pn, pd, pu, pc, aym, ayp, azm, azp, diag);
+}
+// FP32: t + (lane l + 1's v) c in one DPP-sourced v_fmac (the compiler
+// folds a shifted operand into a multiply but not into an fmac).  The
+// s_nop covers the two wait states a DPP read needs after a VALU write of
+// its source.
+__device__ __forceinline__ float fma_from_right(float v, float c, float t) {
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "+v"(t)
+      : "v"(v), "v"(c));
+  return t;
+}
+__device__ __forceinline__ float stencil(float pc, float ps, float pn, float pd, float pu, float axm, float axp,
+                                         float aym, float ayp, float azm, float azp, float diag) {
+  float t = from_left(pc) * axm;
+  t = fma_from_right(pc, axp, t);
+  return stencil_chain(t, ps, pn, pd, pu, pc, aym, ayp, azm, azp, diag);
+}
+
+// acc + r^2 in FP64 (r^2 is exact).  A cell that does not count passes
+// r = 0 (r times a 0 / 1 ownership factor), which leaves acc unchanged.
+__device__ __forceinline__ double add_sq(float r, double acc) {
+  const double d = r;
+  return __builtin_fma(d, d, acc);
+}
+__device__ __forceinline__ double add_sq(double r, double acc) { return __builtin_fma(r, r, acc); }
 
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -121,12 +153,18 @@ __device__ __forceinline__ Plane plane_at(const T* p, long elems, long) {
   asm volatile("" : "+s"(q));
   return Plane{q};
 }
+// The offset is made opaque in place at each use as well, so its widening
+// to 64 bits stays next to the access (a 64-bit offset hoisted out of the
+// loop would cost one 64-bit address add per access; an opaque copy would
+// cost a move).
 template <class T>
-__device__ __forceinline__ T ld_plane(const Plane& b, unsigned off, T*) {
+__device__ __forceinline__ T ld_plane(const Plane& b, unsigned& off, T*) {
+  asm volatile("" : "+v"(off));
   return *(const NS_GLOBAL T*)(b.b + off);
 }
 template <class T>
-__device__ __forceinline__ void st_plane(const Plane& b, unsigned off, T v) {
+__device__ __forceinline__ void st_plane(const Plane& b, unsigned& off, T v) {
+  asm volatile("" : "+v"(off));
   *(NS_GLOBAL T*)(b.b + off) = v;
 }
 
@@ -143,7 +181,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   constexpr int H = 2 * NS;
   constexpr int TX = kLanes - 2 * H;
   constexpr int ROWS = R * W;
-  constexpr int kRing = ring_of<T, W>();
+  constexpr int kRing = ring_of<T, R, W>();
   constexpr int TY = ROWS - 2 * H;
   const int tx = threadIdx.x;
   const int wy = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
@@ -162,6 +200,11 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   auto aym = [&](int j) -> T { return (j > 1 || per1) ? idy2 : T(0); };
   auto ayp = [&](int j) -> T { return (j < g.ny || per1) ? idy2 : T(0); };
   auto owny = [&](int r) -> bool { return wy * R + r >= H && wy * R + r < ROWS - H && j0 + r <= g.ny; };
+  // 1 where row r's cell of this lane is one the tile owns (its residual
+  // counts), 0 on the halo
+  T ownf[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) ownf[r] = owny(r) && ownx ? T(1) : T(0);
   // diagonal a_c and relaxation factor omega / a_c of row r's cell with both
   // z neighbours (d2, w2) or one (d1, w1, planes next to a z wall)
   auto dxy_of = [&](int j) -> double {
@@ -254,8 +297,9 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
     }
   };
 
-  auto step = [&](auto Sc, auto Fc, int L) {
+  auto step = [&](auto Sc, auto Fc, auto Ic, int L) {
     constexpr int S = decltype(Sc)::value;
+    constexpr bool IN = decltype(Ic)::value;  // every stage plane of the step lies in the chunk
     constexpr int SP = S & 1;
     T(&pm2)[R] = P[S];
     T(&pm1)[R] = P[(S + 1) % kRing];
@@ -284,10 +328,10 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
         const T pn = r < R - 1 ? pm1[r + 1] : inB;
         T dg, wg;
         coef(Fc, r, a, (S & 1) ? wA[r] : wB[r], dg, wg);
-        const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, pm2[r], p0[r], axm, axp, aym(j0 + r),
+        const T res = stencil(pc, ps, pn, pm2[r], p0[r], axm, axp, aym(j0 + r),
                               ayp(j0 + r), azm, azp, dg) -
                       qm1[r];
-        if (in_chunk && owny(r) && ownx) acc1 += (double)res * (double)res;
+        acc1 = add_sq(res * (IN || in_chunk ? ownf[r] : T(0)), acc1);
         X1n[r] = fmaT(wg, res, pc);
       }
     }
@@ -304,7 +348,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
         const T pn = r < R - 1 ? X1b[r + 1] : x1B;
         T dg, wg;
         coef(Fc, r, b, (S & 1) ? wA[r] : wB[r], dg, wg);
-        const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, X1a[r], X1n[r], axm, axp, aym(j0 + r),
+        const T res = stencil(pc, ps, pn, X1a[r], X1n[r], axm, axp, aym(j0 + r),
                               ayp(j0 + r), azm, azp, dg) -
                       qm2[r];
         Mn[r] = fmaT(wg, res, pc);
@@ -335,10 +379,10 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
           const T pn = r < R - 1 ? Mb[r + 1] : mB;
           T dg, wg;
           coef(Fc, r, c, (S & 1) ? wA[r] : wB[r], dg, wg);
-          const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, Ma[r], Mn[r], axm, axp, aym(j0 + r),
+          const T res = stencil(pc, ps, pn, Ma[r], Mn[r], axm, axp, aym(j0 + r),
                                 ayp(j0 + r), azm, azp, dg) -
                         hC[r];
-          if (in_chunk && owny(r) && ownx) acc2 += (double)res * (double)res;
+          acc2 = add_sq(res * (IN || in_chunk ? ownf[r] : T(0)), acc2);
           X2n[r] = fmaT(wg, res, pc);
         }
       }
@@ -355,7 +399,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
           const T pn = r < R - 1 ? X2b[r + 1] : x2B;
           T dg, wg;
           coef(Fc, r, d, (S & 1) ? wA[r] : wB[r], dg, wg);
-          const T res = stencil(pc, from_left(pc), from_right(pc), ps, pn, X2a[r], X2n[r], axm, axp, aym(j0 + r),
+          const T res = stencil(pc, ps, pn, X2a[r], X2n[r], axm, axp, aym(j0 + r),
                                 ayp(j0 + r), azm, azp, dg) -
                         hD[r];
           out[r] = fmaT(wg, res, pc);
@@ -412,29 +456,40 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   using F5 = std::integral_constant<int, 5>;
   using FAST = std::true_type;
   using GEN = std::false_type;
+  // steps whose residual planes (L - 1, and L - 3 for two sweeps) all lie
+  // in [z0, z1] need no chunk test
+  const int in_lo = z0 + 2 * NS - 1, in_hi = z1 + 1;
+  using IN = std::true_type;
+  using MASK = std::false_type;
+  auto trip = [&](auto Fc, auto Ic, int L) {
+    step(F0{}, Fc, Ic, L);
+    step(F1{}, Fc, Ic, L + 1);
+    step(F2{}, Fc, Ic, L + 2);
+    step(F3{}, Fc, Ic, L + 3);
+    if constexpr (kRing > 4) {
+      step(F4{}, Fc, Ic, L + 4);
+      step(F5{}, Fc, Ic, L + 5);
+    }
+  };
   for (int L = Lbeg; L <= Lend; L += kRing) {
     if (L >= fast_lo && L + kRing - 1 <= fast_hi) {
-      step(F0{}, FAST{}, L);
-      step(F1{}, FAST{}, L + 1);
-      step(F2{}, FAST{}, L + 2);
-      step(F3{}, FAST{}, L + 3);
-      if constexpr (kRing > 4) {
-        step(F4{}, FAST{}, L + 4);
-        step(F5{}, FAST{}, L + 5);
-      }
+      if (L >= in_lo && L + kRing - 1 <= in_hi)
+        trip(FAST{}, IN{}, L);
+      else
+        trip(FAST{}, MASK{}, L);
     } else {
-      step(F0{}, GEN{}, L);
+      step(F0{}, GEN{}, MASK{}, L);
       if (L + 1 > Lend) break;
-      step(F1{}, GEN{}, L + 1);
+      step(F1{}, GEN{}, MASK{}, L + 1);
       if (L + 2 > Lend) break;
-      step(F2{}, GEN{}, L + 2);
+      step(F2{}, GEN{}, MASK{}, L + 2);
       if (L + 3 > Lend) break;
-      step(F3{}, GEN{}, L + 3);
+      step(F3{}, GEN{}, MASK{}, L + 3);
       if constexpr (kRing > 4) {
         if (L + 4 > Lend) break;
-        step(F4{}, GEN{}, L + 4);
+        step(F4{}, GEN{}, MASK{}, L + 4);
         if (L + 5 > Lend) break;
-        step(F5{}, GEN{}, L + 5);
+        step(F5{}, GEN{}, MASK{}, L + 5);
       }
     }
   }
@@ -511,7 +566,8 @@ k_sor_pass(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restric
       const int col = (int)(q0 / g.nz);
       const int z0 = (int)(q0 - (long)col * g.nz) + 1;
       const int z1 = (int)min((long)g.nz, (long)z0 + (q1 - q0) - 1);
-      pass_tile<T, NS, R, W, ZIN>(p_in, p_out, rhs, g, omega, write, col, z0, z1, ntx, E, acc1, acc2);
+      pass_tile<T, NS, R, W, ZIN>(p_in, p_out, rhs, g, omega, write, col, z0, z1, ntx, E, acc1,
+                                  acc2);
       __syncthreads();
       q0 += z1 - z0 + 1;
     }
@@ -573,39 +629,39 @@ k_pass_batched(const BatchItem* __restrict__ items, int nitems, int m, int q, in
   }
 }
 
-template <class T, int NS, int W>
+template <class T, int NS, int R, int W>
 int pass_resident() {
   static int cached = 0;
   if (cached > 0) return cached;
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sor_pass<T, NS, kRows, W, false>, kLanes * W, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sor_pass<T, NS, R, W, false>, kLanes * W, 0) !=
       hipSuccess)
     return 0;
   cached = cus * (per_cu > 0 ? per_cu : 1);
   return cached;
 }
 
-template <class T, int NS, int W>
+template <class T, int NS, int R, int W>
 hipError_t launch_w(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl, double* part,
                     double omega, int m, int itermax, int write, int zero_in, int inner, int zc) {
   constexpr int H = 2 * NS;
-  constexpr int ROWS = kRows * W;
+  constexpr int ROWS = R * W;
   const int ntx = (g.nx + (kLanes - 2 * H) - 1) / (kLanes - 2 * H);
   const int nty = (g.ny + (ROWS - 2 * H) - 1) / (ROWS - 2 * H);
   // zc = 0: as many workgroups as are resident (each with a balanced share),
   // but no more than there are plane-columns
   const long ntiles_l = zc > 0 ? (long)ntx * nty * ((g.nz + zc - 1) / zc) : (long)ntx * nty * g.nz;
   const int ntiles = (int)(ntiles_l < (1L << 30) ? ntiles_l : (1L << 30));
-  int nb = pass_resident<T, NS, W>();
+  int nb = pass_resident<T, NS, R, W>();
   if (nb <= 0 || nb > ntiles) nb = ntiles;
   const dim3 blk(kLanes, W);
   if (zero_in)
-    k_sor_pass<T, NS, kRows, W, true><<<nb, blk, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write,
+    k_sor_pass<T, NS, R, W, true><<<nb, blk, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write,
                                                           inner, zc, ntx, nty, ntiles);
   else
-    k_sor_pass<T, NS, kRows, W, false><<<nb, blk, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write,
+    k_sor_pass<T, NS, R, W, false><<<nb, blk, 0, st>>>(p_in, p_out, rhs, g, ctl, part, omega, m, itermax, write,
                                                            inner, zc, ntx, nty, ntiles);
   return hipGetLastError();
 }
@@ -621,34 +677,40 @@ template <class T, int NS>
 hipError_t launch_ns(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl, double* part,
                      double omega, int m, int itermax, int write, int zero_in, int inner, int zc, int rows) {
   if (rows == 16)
-    return launch_w<T, NS, 8>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+    return launch_w<T, NS, 2, 8>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
   if constexpr (sizeof(T) == 4) {
+    constexpr int R24 = kR24, R32 = kR32;
     if (rows == 24)
-      return launch_w<T, NS, 12>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+      return launch_w<T, NS, R24, 24 / R24>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in,
+                                            inner, zc);
     if (rows == 32)
-      return launch_w<T, NS, 16>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
+      return launch_w<T, NS, R32, 32 / R32>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in,
+                                            inner, zc);
   }
   return hipErrorInvalidValue;
 }
 
-template <class T, int NS, int W>
+template <class T, int NS, int R, int W>
 hipError_t launch_batched_w(hipStream_t st, const BatchItem* items, int nitems, int nblocks, int m, int q,
                             int zero_in, int force) {
   const dim3 blk(kLanes, W);
   if (zero_in)
-    k_pass_batched<T, NS, kRows, W, true><<<nblocks, blk, 0, st>>>(items, nitems, m, q, force);
+    k_pass_batched<T, NS, R, W, true><<<nblocks, blk, 0, st>>>(items, nitems, m, q, force);
   else
-    k_pass_batched<T, NS, kRows, W, false><<<nblocks, blk, 0, st>>>(items, nitems, m, q, force);
+    k_pass_batched<T, NS, R, W, false><<<nblocks, blk, 0, st>>>(items, nitems, m, q, force);
   return hipGetLastError();
 }
 
 template <class T, int NS>
 hipError_t launch_batched_ns(hipStream_t st, const BatchItem* items, int nitems, int nblocks, int rows, int m,
                              int q, int zero_in, int force) {
-  if (rows == 16) return launch_batched_w<T, NS, 8>(st, items, nitems, nblocks, m, q, zero_in, force);
+  if (rows == 16) return launch_batched_w<T, NS, 2, 8>(st, items, nitems, nblocks, m, q, zero_in, force);
   if constexpr (sizeof(T) == 4) {
-    if (rows == 24) return launch_batched_w<T, NS, 12>(st, items, nitems, nblocks, m, q, zero_in, force);
-    if (rows == 32) return launch_batched_w<T, NS, 16>(st, items, nitems, nblocks, m, q, zero_in, force);
+    constexpr int R24 = kR24, R32 = kR32;
+    if (rows == 24)
+      return launch_batched_w<T, NS, R24, 24 / R24>(st, items, nitems, nblocks, m, q, zero_in, force);
+    if (rows == 32)
+      return launch_batched_w<T, NS, R32, 32 / R32>(st, items, nitems, nblocks, m, q, zero_in, force);
   }
   return hipErrorInvalidValue;
 }
@@ -695,11 +757,14 @@ int pass_max_partials(const Geo& g) {
 
 int pass_resident_groups(int ty, bool f32, int ns) {
   if (ty == 16)
-    return ns == 1 ? (f32 ? pass_resident<float, 1, 8>() : pass_resident<double, 1, 8>())
-                   : (f32 ? pass_resident<float, 2, 8>() : pass_resident<double, 2, 8>());
+    return ns == 1 ? (f32 ? pass_resident<float, 1, 2, 8>() : pass_resident<double, 1, 2, 8>())
+                   : (f32 ? pass_resident<float, 2, 2, 8>() : pass_resident<double, 2, 2, 8>());
   if (!f32) return 0;  // FP64 tiles have 16 rows
-  if (ty == 24) return ns == 1 ? pass_resident<float, 1, 12>() : pass_resident<float, 2, 12>();
-  if (ty == 32) return ns == 1 ? pass_resident<float, 1, 16>() : pass_resident<float, 2, 16>();
+  constexpr int R24 = kR24, R32 = kR32;
+  if (ty == 24)
+    return ns == 1 ? pass_resident<float, 1, R24, 24 / R24>() : pass_resident<float, 2, R24, 24 / R24>();
+  if (ty == 32)
+    return ns == 1 ? pass_resident<float, 1, R32, 32 / R32>() : pass_resident<float, 2, R32, 32 / R32>();
   return 0;
 }
 
