@@ -97,7 +97,11 @@ typedef struct {
   int32_t precision;      /* NS_FP64 or NS_MIXED */
   int32_t checkpoint_every; /* > 0: record checkpoints every k steps for ns_backward */
   int32_t flags;          /* NS_ALLOW_UNSTABLE | NS_TIMING */
-  int32_t tile[2];        /* SOR sweep shape: {rows, z planes per chunk (0 = whole column)}.
+  int32_t tile[2];        /* SOR sweep shape: {rows, z chunk}.  z chunk k > 0: chunks of k
+                             planes; k < 0: each domain split into the fewest equal chunks of
+                             at most -k planes; 0: the whole column (two-sweep shapes on a
+                             single-domain handle: an equal share of the plane-columns per
+                             resident workgroup).
                              rows 4, 8 or 12: one sweep per launch, that many interior rows
                              per workgroup; rows 16, 24 or 32 (NS_FP64: 16 only): two
                              sweeps per launch (temporal blocking), that many rows per
@@ -130,7 +134,9 @@ typedef struct {
   double ms[NS_T_COUNT];
   int64_t launches[NS_T_COUNT];
   int64_t sor_bytes;     /* algorithmic HBM bytes of the SOR launches timed */
-  int32_t sor_tile[2];   /* sweep shape in use on instance 0 (see ns_params.tile) */
+  int32_t sor_tile[2];   /* sweep shape in use on instance 0 (see ns_params.tile); a batched
+                            handle may report sor_tile[1] = -k: each domain split into the
+                            fewest equal z chunks of at most k planes */
 } ns_timing;
 
 /* Fill *p with the defaults of the 16^3 lid-driven cavity (Re 100, dt 0.01,

@@ -176,6 +176,18 @@ struct BatchItem {
   int budget;      // the solve stops at iterate `budget` at the latest
   int inner;       // 1: correction solve (stop at ctl->thr_in)
 };
+// Planes per z chunk of a domain with nz planes: zc > 0 fixed chunks of zc
+// planes, zc = 0 the whole column, zc < 0 the fewest chunks of at most -zc
+// planes, equally long (so the tiles of domains of different heights come
+// out of similar length).
+inline int item_chunk(int nz, int zc) {
+  if (zc > 0) return zc < nz ? zc : nz;
+  if (zc < 0) {
+    const int parts = (nz - zc - 1) / (-zc);
+    return (nz + parts - 1) / parts;
+  }
+  return nz;
+}
 // Fill ntx, nty, zc and ntiles of an item for a sweep shape.
 void batch_item_shape(BatchItem& it, int ty, int zc);
 // One sweep of every domain of a batch in one launch (nblocks = sum of ntiles).

@@ -199,7 +199,6 @@ ns_status validate(const ns_params& p, int idx) {
   if (!(p.tile[0] == -1 || p.tile[0] == 0 || p.tile[0] == 4 || p.tile[0] == 8 || p.tile[0] == 12 ||
         p.tile[0] == 16 || p.tile[0] == 24 || p.tile[0] == 32))
     return bad("tile[0] must be -1, 0, 4, 8, 12, 16, 24 or 32");
-  if (p.tile[1] < 0) return bad("tile[1] must be >= 0");
   if (p.tile[0] > 0 && (double)(p.nx + 2) * (p.ny + 2) * (p.precision == NS_MIXED ? 4 : 8) >= 2147483648.0)
     return bad("planes this large need the unfused sweeps (tile = {-1, 0})");
   if (p.tile[0] > 16 && p.precision == NS_FP64)
@@ -331,10 +330,31 @@ ns_status autotune(ns_solver* s, Inst& I) {
   return NS_OK;
 }
 
+// Puts the items of a batch table in order of decreasing chunk length
+// (stable) and numbers their workgroups.  Workgroups start in index order as
+// compute units free up, so a launch whose longest tiles start first does
+// not end waiting on one long tile that started last (longest-first list
+// scheduling).  Returns the permutation: table entry k is the caller's item
+// ord[k].
+std::vector<int> order_longest_first(BatchItem* items, int n) {
+  std::vector<int> ord(n);
+  for (int k = 0; k < n; k++) ord[k] = k;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return items[a].zc > items[b].zc; });
+  std::vector<BatchItem> tmp(items, items + n);
+  int nb = 0;
+  for (int k = 0; k < n; k++) {
+    items[k] = tmp[ord[k]];
+    items[k].first = nb;
+    nb += items[k].ntiles;
+  }
+  return ord;
+}
+
 // Batch shape: time the one-sweep rows 4 / 8 / 12 and the two-sweep pass
-// rows 16 / 24 / 32 (per sweep) x z chunk whole / 32 / 16 with one batched
-// launch each over all instances (zero buffers, a scratch control array
-// that never converges), keep the fastest.
+// rows 16 / 24 / 32 (per sweep) x z chunks (whole column, 32, 16, and
+// chunks of at most 48 planes balanced per domain) with one batched launch
+// each over all instances (zero buffers, a scratch control array that
+// never converges), keep the fastest.
 template <class T>
 ns_status tune_batch_run(ns_solver* s, Ctl* tctl, int ty, int zc, float* ms) {
   const int n = (int)s->in.size();
@@ -354,9 +374,9 @@ ns_status tune_batch_run(ns_solver* s, Ctl* tctl, int ty, int zc, float* ms) {
     it.inner = 0;
     if (ty >= 16) pass_item_shape(it, ty, zc, 2);
     else batch_item_shape(it, ty, zc);
-    it.first = nblocks;
     nblocks += it.ntiles;
   }
+  (void)order_longest_first(s->items_h, n);
   HCK(s, hipMemcpyAsync(s->items_d, s->items_h, sizeof(BatchItem) * n, hipMemcpyHostToDevice, s->stream));
   hipEvent_t a, b;
   HCK(s, hipEventCreate(&a));
@@ -386,11 +406,11 @@ ns_status autotune_batch(ns_solver* s) {
   bool pass_ok = true;
   for (auto& I : s->in) pass_ok &= pass_grid_ok(I.g, I.esz);
   const int rows[6] = {4, 8, 12, 16, 24, 32};
-  const int zcs[3] = {0, 32, 16};
+  const int zcs[4] = {0, 32, 16, -48};
   float best = 1e30f;
   ns_status st = NS_OK;
   for (int r = 0; r < 6 && st == NS_OK; r++)
-    for (int z = 0; z < 3 && st == NS_OK; z++) {
+    for (int z = 0; z < 4 && st == NS_OK; z++) {
       if (rows[r] >= 16 && (!pass_ok || !pass_rows_ok(rows[r], s->in[0].mixed))) continue;
       float ms = 0.f;
       st = s->in[0].mixed ? tune_batch_run<float>(s, tctl, rows[r], zcs[z], &ms)
@@ -799,9 +819,7 @@ ns_status run_batched_pass(ns_solver* s, int n, int max_budget, int pred, int ze
   int nblocks = 0;
   long long cells = 0;
   for (int q = 0; q < n; q++) {
-    BatchItem& it = s->items_h[q];
-    pass_item_shape(it, rows, s->batch_zc, 2);
-    it.first = nblocks;
+    const BatchItem& it = s->items_h[q];
     nblocks += it.ntiles;
     cells += (long long)it.g.nx * it.g.ny * it.g.nz;
   }
@@ -877,14 +895,12 @@ ns_status run_batched_pass(ns_solver* s, int n, int max_budget, int pred, int ze
 // item is done; bpc = algorithmic bytes per cell of one sweep; fbuf[q]
 // receives the buffer of item q's accepted iterate.
 template <class T>
-ns_status run_batched(ns_solver* s, int n, int max_budget, int pred, int zero_first, long long bpc,
-                      const std::vector<int>& idx_of_item, std::vector<int>& fbuf) {
-  if (s->batch_ty >= 16) return run_batched_pass<T>(s, n, max_budget, pred, zero_first, bpc, idx_of_item, fbuf);
+ns_status run_batched_sweeps(ns_solver* s, int n, int max_budget, int pred, int zero_first, long long bpc,
+                             const std::vector<int>& idx_of_item, std::vector<int>& fbuf) {
   int nblocks = 0;
   long long cells = 0;
   for (int q = 0; q < n; q++) {
-    BatchItem& it = s->items_h[q];
-    it.first = nblocks;
+    const BatchItem& it = s->items_h[q];
     nblocks += it.ntiles;
     cells += (long long)it.g.nx * it.g.ny * it.g.nz;
   }
@@ -923,6 +939,23 @@ ns_status run_batched(ns_solver* s, int n, int max_budget, int pred, int zero_fi
   }
   fbuf.resize(n);
   for (int q = 0; q < n; q++) fbuf[q] = (s->items_h[q].cur + s->hctl[idx_of_item[q]].final_) & 1;
+  return NS_OK;
+}
+
+template <class T>
+ns_status run_batched(ns_solver* s, int n, int max_budget, int pred, int zero_first, long long bpc,
+                      const std::vector<int>& idx_of_item, std::vector<int>& fbuf) {
+  const bool pass = s->batch_ty >= 16;
+  if (pass)
+    for (int q = 0; q < n; q++) pass_item_shape(s->items_h[q], s->batch_ty, s->batch_zc, 2);
+  const std::vector<int> ord = order_longest_first(s->items_h, n);
+  std::vector<int> idx(n), fb;
+  for (int k = 0; k < n; k++) idx[k] = idx_of_item[ord[k]];
+  const ns_status e = pass ? run_batched_pass<T>(s, n, max_budget, pred, zero_first, bpc, idx, fb)
+                           : run_batched_sweeps<T>(s, n, max_budget, pred, zero_first, bpc, idx, fb);
+  if (e != NS_OK) return e;
+  fbuf.assign(n, 0);
+  for (int k = 0; k < n; k++) fbuf[ord[k]] = fb[k];
   return NS_OK;
 }
 

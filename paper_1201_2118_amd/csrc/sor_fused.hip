@@ -423,7 +423,7 @@ hipError_t launch_batched_ty(hipStream_t st, const BatchItem* items, int nitems,
 
 int fused_num_blocks(const Geo& g, const SorShape& s) {
   const int ty = s.ty;
-  const int zc = s.zc > 0 ? s.zc : g.nz;
+  const int zc = item_chunk(g.nz, s.zc);
   return ((g.nx + kTX - 1) / kTX) * ((g.ny + ty - 1) / ty) * ((g.nz + zc - 1) / zc);
 }
 
@@ -444,7 +444,7 @@ template <class T>
 hipError_t launch_sor_fused(hipStream_t st, const Geo& g, const T* p_in, T* p_out, const T* rhs, Ctl* ctl,
                             double* part, double omega, int m, int itermax, int write, int zero_in, int inner,
                             const SorShape& s) {
-  const int zc = s.zc > 0 ? (s.zc < g.nz ? s.zc : g.nz) : g.nz;
+  const int zc = item_chunk(g.nz, s.zc);
   switch (s.ty) {
     case 4: return launch_ty<T, 8>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
     case 8: return launch_ty<T, 12>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc);
@@ -465,7 +465,7 @@ namespace ns {
 void batch_item_shape(BatchItem& it, int ty, int zc) {
   it.ntx = (it.g.nx + kTX - 1) / kTX;
   it.nty = (it.g.ny + ty - 1) / ty;
-  it.zc = zc > 0 ? (zc < it.g.nz ? zc : it.g.nz) : it.g.nz;
+  it.zc = item_chunk(it.g.nz, zc);
   it.ntiles = it.ntx * it.nty * ((it.g.nz + it.zc - 1) / it.zc);
 }
 

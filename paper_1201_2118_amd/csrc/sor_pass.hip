@@ -721,7 +721,7 @@ void pass_item_shape(BatchItem& it, int rows, int zc, int ns) {
   const int h = 2 * ns;
   it.ntx = (it.g.nx + (kLanes - 2 * h) - 1) / (kLanes - 2 * h);
   it.nty = (it.g.ny + (rows - 2 * h) - 1) / (rows - 2 * h);
-  it.zc = zc > 0 ? (zc < it.g.nz ? zc : it.g.nz) : it.g.nz;
+  it.zc = item_chunk(it.g.nz, zc);
   it.ntiles = it.ntx * it.nty * ((it.g.nz + it.zc - 1) / it.zc);
 }
 
@@ -780,7 +780,7 @@ hipError_t launch_sor_pass(hipStream_t st, const Geo& g, const T* p_in, T* p_out
                            double* part, double omega, int m, int itermax, int write, int zero_in, int inner,
                            int ns, const SorShape& s) {
   // zc = 0: balanced z ranges over the resident workgroups
-  const int zc = s.zc > 0 ? (s.zc < g.nz ? s.zc : g.nz) : 0;
+  const int zc = s.zc != 0 ? item_chunk(g.nz, s.zc) : 0;
   if (ns == 1) return launch_ns<T, 1>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc, s.ty);
   if (ns == 2) return launch_ns<T, 2>(st, g, p_in, p_out, rhs, ctl, part, omega, m, itermax, write, zero_in, inner, zc, s.ty);
   return hipErrorInvalidValue;

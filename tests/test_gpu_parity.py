@@ -125,7 +125,7 @@ def test_restart_and_determinism_are_bitwise():
         assert np.array_equal(a.get_np(f), d.get_np(f)), f
 
 
-@pytest.mark.parametrize("tile", [None, (8, 0), (16, 0), (16, 5), (24, 5), (32, 0)])
+@pytest.mark.parametrize("tile", [None, (8, 0), (16, 0), (16, 5), (24, 5), (32, 0), (16, -7), (32, -12), (8, -5)])
 @pytest.mark.parametrize("form", ["fp64", "mixed"])
 def test_batched_instances_match_standalone_runs_and_oracle(form, tile):
     """Several domains in one handle share one launch per sweep (one-sweep
@@ -282,7 +282,7 @@ def test_backward_needs_a_recording():
 
 # ---- fused sweep shapes ------------------------------------------------------------
 
-@pytest.mark.parametrize("tile", [(4, 0), (8, 5), (12, 3), (8, 1), (4, 2)])
+@pytest.mark.parametrize("tile", [(4, 0), (8, 5), (12, 3), (8, 1), (4, 2), (8, -4)])
 @pytest.mark.parametrize("dims,bc", [((70, 20, 13), (0, 0, 0)), ((16, 12, 8), (1, 1, 1)),
                                      ((61, 10, 7), (0, 1, 0)), ((3, 130, 4), (0, 0, 0)),
                                      ((122, 7, 6), (1, 0, 1))])
@@ -305,7 +305,7 @@ def test_fused_sweep_shapes_match_unfused_and_oracle(dims, bc, tile):
 
 # ---- two-sweep pass shapes (temporal blocking) ----------------------------------
 
-@pytest.mark.parametrize("tile", [(16, 0), (16, 5), (16, 3), (16, 1), (16, 2)])
+@pytest.mark.parametrize("tile", [(16, 0), (16, 5), (16, 3), (16, 1), (16, 2), (16, -4)])
 @pytest.mark.parametrize("dims,bc", [((70, 20, 13), (0, 0, 0)), ((16, 12, 8), (1, 1, 1)),
                                      ((61, 10, 7), (0, 1, 0)), ((3, 130, 4), (0, 0, 0)),
                                      ((122, 7, 6), (1, 0, 1)), ((130, 40, 9), (0, 0, 0))])
@@ -368,7 +368,7 @@ def test_pass_periodic_taylor_green():
     U.compare_state(s, o, prm, 1e-12)
 
 
-@pytest.mark.parametrize("tile", [(4, 16), (12, 0), (16, 0), (32, 5), (24, 3), (32, 1), (24, 0)])
+@pytest.mark.parametrize("tile", [(4, 16), (12, 0), (16, 0), (32, 5), (24, 3), (32, 1), (24, 0), (32, -6)])
 def test_fused_mixed_precision_shapes(tile):
     prm = W.cavity(70, ny=24, nz=20, dt=0.002)
     a = U.gpu_run(dict(prm, precision="mixed", tile=tile), 2)
