@@ -172,14 +172,15 @@ __device__ __forceinline__ double flux(double t, double a, double b, double gamm
 }
 
 template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_fgh(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
-      const T* __restrict__ fx, const T* __restrict__ fy, const T* __restrict__ fz,
-      T* __restrict__ F, T* __restrict__ G, T* __restrict__ H, Geo g, const Ctl* __restrict__ ctl,
-      double nu, double gamma, double gx, double gy, double gz) {
+__device__ __forceinline__ void fgh_cells(const Geo& g, int zr, const CellBlk& blk, const T* __restrict__ u,
+                                          const T* __restrict__ v, const T* __restrict__ w,
+                                          const T* __restrict__ fx, const T* __restrict__ fy,
+                                          const T* __restrict__ fz, T* __restrict__ F, T* __restrict__ G,
+                                          T* __restrict__ H, const Ctl* __restrict__ ctl, double nu, double gamma,
+                                          double gx, double gy, double gz) {
   const double dt = ctl->dt;
   const long sx = g.sx, sxy = g.sxy;
-  for_cells(g, zr, [&](int ci, int cj, int ck, long c) {
+  for_cells(g, zr, blk, [&](int ci, int cj, int ck, long c) {
     if (ci <= g.hi[0]) {  // F on the x face i
       const double q = u[c], qe = u[c + 1], qw = u[c - 1], qn = u[c + sx], qs = u[c - sx],
                    qt = u[c + sxy], qb = u[c - sxy];
@@ -228,6 +229,15 @@ k_fgh(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restr
   });
 }
 
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_fgh(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
+      const T* __restrict__ fx, const T* __restrict__ fy, const T* __restrict__ fz,
+      T* __restrict__ F, T* __restrict__ G, T* __restrict__ H, Geo g, const Ctl* __restrict__ ctl,
+      double nu, double gamma, double gx, double gy, double gz) {
+  fgh_cells<T>(g, zr, own_blk(), u, v, w, fx, fy, fz, F, G, H, ctl, nu, gamma, gx, gy, gz);
+}
+
 // ---------------------------------------------------------------------------
 // Poisson right-hand side rhs = (div F) / dt on every cell (the face below
 // cell 1 of a periodic axis is face n), with the RMS of rhs reduced into the
@@ -235,15 +245,14 @@ k_fgh(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restr
 // finishes the solve before any sweep.  dt_scale_one != 0 uses dt = 1 (the
 // adjoint projection).
 template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_rhs(int zr, const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
-      T* __restrict__ rhs, Geo g, Ctl* ctl, double* part, double tol, int unit_dt) {
-  __shared__ double sh[16];
-  __shared__ int sh_last;
+__device__ __forceinline__ void rhs_cells(const Geo& g, int zr, const CellBlk& blk, const T* __restrict__ F,
+                                          const T* __restrict__ G, const T* __restrict__ H, T* __restrict__ rhs,
+                                          Ctl* ctl, double* part, double tol, int unit_dt, double* sh,
+                                          int* sh_last) {
   const double idt = unit_dt ? 1.0 : 1.0 / ctl->dt;
   const long n = (long)g.nx * g.ny * g.nz;
   double acc = 0.0;
-  for_cells(g, zr, [&](int ci, int cj, int ck, long c) {
+  for_cells(g, zr, blk, [&](int ci, int cj, int ck, long c) {
     const long cw = (ci > 1 || !g.per[0]) ? c - 1 : c + (g.nx - 1);
     const long cs = (cj > 1 || !g.per[1]) ? c - g.sx : c + (long)(g.ny - 1) * g.sx;
     const long cb = (ck > 1 || !g.per[2]) ? c - g.sxy : c + (long)(g.nz - 1) * g.sxy;
@@ -253,11 +262,9 @@ k_rhs(int zr, const T* __restrict__ F, const T* __restrict__ G, const T* __restr
     rhs[c] = r;
     acc += (double)r * (double)r;
   });
-  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  const unsigned nbk = gridDim.x * gridDim.y * gridDim.z;
   double s = block_sum(acc, sh);
-  if (publish_partial(part, bid, s, ctl, nbk, &sh_last)) {
-    double tot = sum_partials(part, nbk, sh);
+  if (publish_partial(part, blk.id, s, ctl, blk.count, sh_last)) {
+    double tot = sum_partials(part, blk.count, sh);
     if (flat_tid() == 0) {
       const double rms = sqrt(tot / (double)n);
       ctl->rhs_rms = rms;
@@ -272,16 +279,25 @@ k_rhs(int zr, const T* __restrict__ F, const T* __restrict__ G, const T* __restr
   }
 }
 
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_rhs(int zr, const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
+      T* __restrict__ rhs, Geo g, Ctl* ctl, double* part, double tol, int unit_dt) {
+  __shared__ double sh[16];
+  __shared__ int sh_last;
+  rhs_cells<T>(g, zr, own_blk(), F, G, H, rhs, ctl, part, tol, unit_dt, sh, &sh_last);
+}
+
 // ---------------------------------------------------------------------------
 // Projection (UPDATE_VELOCITY): u = F - dt (p[+x] - p) / dx on the unknowns
 // of each component; p ghosts hold periodic images where needed.
 template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_project(int zr, const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
-          const double* __restrict__ p, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w,
-          Geo g, const Ctl* __restrict__ ctl, int unit_dt) {
+__device__ __forceinline__ void project_cells(const Geo& g, int zr, const CellBlk& blk, const T* __restrict__ F,
+                                              const T* __restrict__ G, const T* __restrict__ H,
+                                              const double* __restrict__ p, T* __restrict__ u, T* __restrict__ v,
+                                              T* __restrict__ w, const Ctl* __restrict__ ctl, int unit_dt) {
   const double dt = unit_dt ? 1.0 : ctl->dt;
-  for_cells(g, zr, [&](int ci, int cj, int ck, long c) {
+  for_cells(g, zr, blk, [&](int ci, int cj, int ck, long c) {
     const double pc = p[c];
     if (ci <= g.hi[0]) u[c] = T((double)F[c] - dt * (p[c + 1] - pc) * g.idx);
     if (cj <= g.hi[1]) v[c] = T((double)G[c] - dt * (p[c + g.sx] - pc) * g.idy);
@@ -289,30 +305,37 @@ k_project(int zr, const T* __restrict__ F, const T* __restrict__ G, const T* __r
   });
 }
 
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_project(int zr, const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
+          const double* __restrict__ p, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w,
+          Geo g, const Ctl* __restrict__ ctl, int unit_dt) {
+  project_cells<T>(g, zr, own_blk(), F, G, H, p, u, v, w, ctl, unit_dt);
+}
+
 // Adaptive step: tau * min(diffusive limit, h_d / max|u_d|) with the maxima
 // over the unknowns and the wall speeds.
 template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_umax(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w, Geo g, Ctl* ctl,
-       double* part, double re, double tau, double wu, double wv, double ww) {
-  __shared__ double sh[16];
-  __shared__ int sh_last;
+__device__ __forceinline__ void umax_cells(const Geo& g, int zr, const CellBlk& blk, const T* __restrict__ u,
+                                           const T* __restrict__ v, const T* __restrict__ w, Ctl* ctl,
+                                           double* part, double re, double tau, double wu, double wv, double ww,
+                                           double* sh, int* sh_last) {
   double m[3] = {0.0, 0.0, 0.0};
-  for_cells(g, zr, [&](int ci, int cj, int ck, long c) {
+  for_cells(g, zr, blk, [&](int ci, int cj, int ck, long c) {
     if (ci <= g.hi[0]) m[0] = fmax(m[0], fabs((double)u[c]));
     if (cj <= g.hi[1]) m[1] = fmax(m[1], fabs((double)v[c]));
     if (ck <= g.hi[2]) m[2] = fmax(m[2], fabs((double)w[c]));
   });
   double r[3];
   for (int d = 0; d < 3; d++) r[d] = block_max(m[d], sh);
-  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+  const unsigned bid = blk.id;
+  const unsigned nb = blk.count;
   if (flat_tid() == 0) {
     part[bid] = r[0];
     part[nb + bid] = r[1];
     part[2 * nb + bid] = r[2];
   }
-  if (publish_partial(part + 3 * nb, bid, 0.0, ctl, nb, &sh_last)) {
+  if (publish_partial(part + 3 * nb, bid, 0.0, ctl, nb, sh_last)) {
     double mm[3];
     for (int d = 0; d < 3; d++) mm[d] = max_partials(part + d * nb, nb, sh);
     if (flat_tid() == 0) {
@@ -328,6 +351,74 @@ k_umax(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __rest
       ctl->ticket = 0;
     }
   }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_umax(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w, Geo g, Ctl* ctl,
+       double* part, double re, double tau, double wu, double wv, double ww) {
+  __shared__ double sh[16];
+  __shared__ int sh_last;
+  umax_cells<T>(g, zr, own_blk(), u, v, w, ctl, part, re, tau, wu, wv, ww, sh, &sh_last);
+}
+
+// ---------------------------------------------------------------------------
+// Batched stages: workgroup b of the launch belongs to the domain whose
+// [first, first + gx gy gz) holds it (binary search of the item table) and
+// takes that domain's block b - first, x fastest.
+__device__ __forceinline__ const StageItem& stage_item(const StageItem* __restrict__ items, int nitems,
+                                                       CellBlk& blk) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= b) lo = mid; else hi = mid - 1;
+  }
+  const StageItem& it = items[lo];
+  const int l = b - it.first;
+  blk.x = l % it.gx;
+  blk.y = (l / it.gx) % it.gy;
+  blk.z = l / (it.gx * it.gy);
+  blk.id = (unsigned)l;
+  blk.count = (unsigned)(it.gx * it.gy * it.gz);
+  return it;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fgh_batched(const StageItem* __restrict__ items, int nitems) {
+  CellBlk blk;
+  const StageItem& it = stage_item(items, nitems, blk);
+  fgh_cells<T>(it.g, it.zr, blk, (const T*)it.in[0], (const T*)it.in[1], (const T*)it.in[2], (const T*)it.in[3],
+               (const T*)it.in[4], (const T*)it.in[5], (T*)it.out[0], (T*)it.out[1], (T*)it.out[2], it.ctl, it.s[0],
+               it.s[1], it.s[2], it.s[3], it.s[4]);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_rhs_batched(const StageItem* __restrict__ items, int nitems) {
+  __shared__ double sh[16];
+  __shared__ int sh_last;
+  CellBlk blk;
+  const StageItem& it = stage_item(items, nitems, blk);
+  rhs_cells<T>(it.g, it.zr, blk, (const T*)it.in[0], (const T*)it.in[1], (const T*)it.in[2], (T*)it.out[0], it.ctl,
+               it.part, it.s[0], 0, sh, &sh_last);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_project_batched(const StageItem* __restrict__ items, int nitems) {
+  CellBlk blk;
+  const StageItem& it = stage_item(items, nitems, blk);
+  project_cells<T>(it.g, it.zr, blk, (const T*)it.in[0], (const T*)it.in[1], (const T*)it.in[2],
+                   (const double*)it.in[3], (T*)it.out[0], (T*)it.out[1], (T*)it.out[2], it.ctl, 0);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_umax_batched(const StageItem* __restrict__ items, int nitems) {
+  __shared__ double sh[16];
+  __shared__ int sh_last;
+  CellBlk blk;
+  const StageItem& it = stage_item(items, nitems, blk);
+  umax_cells<T>(it.g, it.zr, blk, (const T*)it.in[0], (const T*)it.in[1], (const T*)it.in[2], it.ctl, it.part,
+                it.s[0], it.s[1], it.s[2], it.s[3], it.s[4], sh, &sh_last);
 }
 
 template <class T>
@@ -441,6 +532,21 @@ hipError_t launch_divergence(hipStream_t st, const Geo& g, const T* u, const T* 
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_stage_batched(hipStream_t st, int kind, const StageItem* d_items, int nitems, int nblocks) {
+  if (nitems <= 0 || nblocks <= 0) return hipSuccess;
+  const dim3 blk(kCellX, kCellY);
+  switch (kind) {
+    case kStageFgh: k_fgh_batched<T><<<nblocks, blk, 0, st>>>(d_items, nitems); break;
+    case kStageRhs: k_rhs_batched<T><<<nblocks, blk, 0, st>>>(d_items, nitems); break;
+    case kStageProject: k_project_batched<T><<<nblocks, blk, 0, st>>>(d_items, nitems); break;
+    case kStageUmax: k_umax_batched<T><<<nblocks, blk, 0, st>>>(d_items, nitems); break;
+    case kStageDefect: return launch_defect_batched(st, d_items, nitems, nblocks);
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_mask_unknowns(hipStream_t st, const Geo& g, double* q, int comp) {
   k_mask<<<grid_for(g.ntot, 1 << 16), kBlock, 0, st>>>(q, g, comp);
   return hipGetLastError();
@@ -459,7 +565,8 @@ hipError_t launch_mask_unknowns(hipStream_t st, const Geo& g, double* q, int com
                                         const double*, T*, T*, T*, const Ctl*, double);             \
   template hipError_t launch_umax<T>(hipStream_t, const Geo&, const T*, const T*, const T*, Ctl*,   \
                                      double*, double, double, const double[6][3]);                  \
-  template hipError_t launch_divergence<T>(hipStream_t, const Geo&, const T*, const T*, const T*, T*);
+  template hipError_t launch_divergence<T>(hipStream_t, const Geo&, const T*, const T*, const T*, T*);       \
+  template hipError_t launch_stage_batched<T>(hipStream_t, int, const StageItem*, int, int);
 
 NS_INST(double)
 NS_INST(float)

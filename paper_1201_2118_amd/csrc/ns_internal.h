@@ -121,17 +121,33 @@ inline dim3 cell_grid(const Geo& g, long target) {
   const int zr = cell_zrun(g, target);
   return dim3(bx, by, (g.nz + zr - 1) / zr);
 }
-// f(i, j, k, c) for every interior cell of this workgroup's (x, y) tile and
+// Position of a cell-kernel workgroup in the workgroup grid of its domain:
+// block (x, y, z), its linear index and the domain's workgroup count (the
+// slot and count of a reduction's partial sums).
+struct CellBlk {
+  int x, y, z;
+  unsigned id, count;
+};
+__device__ __forceinline__ CellBlk own_blk() {
+  return CellBlk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z,
+                 blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                 gridDim.x * gridDim.y * gridDim.z};
+}
+// f(i, j, k, c) for every interior cell of workgroup b's (x, y) tile and
 // run of zr planes.
 template <class F>
-__device__ __forceinline__ void for_cells(const Geo& g, int zr, F&& f) {
-  const int i = blockIdx.x * kCellX + threadIdx.x + 1;
-  const int j = blockIdx.y * kCellY + threadIdx.y + 1;
+__device__ __forceinline__ void for_cells(const Geo& g, int zr, const CellBlk& b, F&& f) {
+  const int i = b.x * kCellX + threadIdx.x + 1;
+  const int j = b.y * kCellY + threadIdx.y + 1;
   if (i > g.nx || j > g.ny) return;
-  const int k0 = blockIdx.z * zr + 1;
+  const int k0 = b.z * zr + 1;
   const int k1 = min(g.nz, k0 + zr - 1);
   long c = (long)k0 * g.sxy + (long)j * g.sx + i;
   for (int k = k0; k <= k1; k++, c += g.sxy) f(i, j, k, c);
+}
+template <class F>
+__device__ __forceinline__ void for_cells(const Geo& g, int zr, F&& f) {
+  for_cells(g, zr, own_blk(), f);
 }
 inline unsigned cell_blocks(const Geo& g, long target) {
   const dim3 d = cell_grid(g, target);
@@ -200,6 +216,46 @@ void pass_item_shape(BatchItem& it, int rows, int zc, int ns);
 template <class T> hipError_t launch_pass_batched(hipStream_t st, const BatchItem* d_items, int nitems,
                                                  int nblocks, int rows, int m, int q, int ns, int zero_in,
                                                  int force);
+
+// One domain of a batched cell-kernel launch (one launch of a stage covers
+// every domain of a batch): the domain's geometry, its workgroups
+// [first, first + gx gy gz) of the launch, planes per workgroup, and the
+// stage's arguments (meaning per stage, see launch_stage_batched).
+struct StageItem {
+  Geo g;
+  int first;
+  int gx, gy, gz, zr;
+  const void* in[6];
+  void* out[3];
+  Ctl* ctl;
+  double* part;
+  double s[6];
+};
+// Host: workgroup grid of a domain for a stage (target = reduction
+// workgroups as for the single-domain launch, 0 without a reduction).
+inline void stage_item_grid(StageItem& it, long target) {
+  const dim3 d = cell_grid(it.g, target);
+  it.gx = (int)d.x;
+  it.gy = (int)d.y;
+  it.gz = (int)d.z;
+  it.zr = cell_zrun(it.g, target);
+}
+enum StageKind { kStageFgh = 0, kStageRhs, kStageProject, kStageUmax, kStageDefect, kStageKinds };
+// Workgroups per domain of each stage: the same grids as the single-domain
+// launchers.
+inline long stage_target(int kind) {
+  return kind == kStageRhs || kind == kStageUmax ? kRedRhs : (kind == kStageDefect ? kRedDefect : 0);
+}
+// One launch of a stage over nitems domains (nblocks = sum of their
+// workgroups), the same per-cell arithmetic as the single-domain kernels.
+//   kStageFgh:     in = u, v, w, fx, fy, fz; out = F, G, H; s = nu, gamma, gx, gy, gz (dt from ctl)
+//   kStageRhs:     in = F, G, H; out = rhs; s = tol (dt from ctl)
+//   kStageProject: in = F, G, H, p (FP64); out = u, v, w (dt from ctl)
+//   kStageUmax:    in = u, v, w; s = re, tau, wall speed x, y, z
+//   kStageDefect:  in = p_in (FP64), e (FP32 or null), rhs (FP32); out = p_out (FP64), r (FP32); s = eta
+template <class T> hipError_t launch_stage_batched(hipStream_t st, int kind, const StageItem* d_items, int nitems,
+                                                  int nblocks);
+hipError_t launch_defect_batched(hipStream_t st, const StageItem* d_items, int nitems, int nblocks);
 
 // Adjoint of the predictor in gather form (FP64 only): z = B^T J_Phi(u)^T mu.
 hipError_t launch_adj_fgh(hipStream_t st, const Geo& g, const double* u, const double* v,

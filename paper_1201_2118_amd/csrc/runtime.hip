@@ -94,6 +94,10 @@ struct ns_solver {
   int batch_ty = 8, batch_zc = 0;
   BatchItem* items_h = nullptr;  // pinned
   BatchItem* items_d = nullptr;
+  // batched cell stages: one table slice per stage kind (a slice is
+  // rewritten only after a stream synchronisation has passed its last copy)
+  StageItem* stage_h = nullptr;  // pinned
+  StageItem* stage_d = nullptr;
   // batched: the per-domain stages (boundary fill, predictor, rhs, defect,
   // projection) are spread over a few library streams so that the small
   // kernels of different domains overlap
@@ -706,27 +710,11 @@ ns_status step_pre(ns_solver* s, int idx, State& S) {
   return NS_OK;
 }
 
-// Stages after the solve: pressure ghosts, projection, boundary fill; then
-// the statistics from the last polled control block.
-template <class T>
-ns_status step_post(ns_solver* s, int idx, State& S, int sweeps, int outer, bool account) {
+// The step's statistics from the last polled control block (and the
+// non-finite check of the solve).
+ns_status step_account(ns_solver* s, int idx, int sweeps, int outer, bool account) {
   Inst& I = s->in[idx];
-  const Geo& g = I.g;
-  const ns_params& p = I.prm;
-  T* u = (T*)S.u;
-  T* v = (T*)S.v;
-  T* w = (T*)S.w;
   const Ctl h = s->hctl[idx];
-  {
-    Timed t(s, NS_T_PROJECT);
-    HCK(s, launch_p_ghosts<double>(s->stream, g, S.p[S.pcur]));
-    HCK(s, launch_project<T>(s->stream, g, (const T*)I.F, (const T*)I.G, (const T*)I.H, S.p[S.pcur], u, v, w,
-                             I.ctl, 0.0));
-  }
-  {
-    Timed t(s, NS_T_BC);
-    HCK(s, launch_bc_vel<T>(s->stream, g, u, v, w, p.wall_vel));
-  }
   if (h.nonfinite) return fail(s, NS_E_NONFINITE, "non-finite residual in the pressure solve");
   if (account) {
     ns_stats& st = I.st;
@@ -740,6 +728,29 @@ ns_status step_post(ns_solver* s, int idx, State& S, int sweeps, int outer, bool
     st.steps++;
   }
   return NS_OK;
+}
+
+// Stages after the solve: pressure ghosts, projection, boundary fill; then
+// the statistics from the last polled control block.
+template <class T>
+ns_status step_post(ns_solver* s, int idx, State& S, int sweeps, int outer, bool account) {
+  Inst& I = s->in[idx];
+  const Geo& g = I.g;
+  const ns_params& p = I.prm;
+  T* u = (T*)S.u;
+  T* v = (T*)S.v;
+  T* w = (T*)S.w;
+  {
+    Timed t(s, NS_T_PROJECT);
+    HCK(s, launch_p_ghosts<double>(s->stream, g, S.p[S.pcur]));
+    HCK(s, launch_project<T>(s->stream, g, (const T*)I.F, (const T*)I.G, (const T*)I.H, S.p[S.pcur], u, v, w,
+                             I.ctl, 0.0));
+  }
+  {
+    Timed t(s, NS_T_BC);
+    HCK(s, launch_bc_vel<T>(s->stream, g, u, v, w, p.wall_vel));
+  }
+  return step_account(s, idx, sweeps, outer, account);
 }
 
 template <class T>
@@ -794,6 +805,37 @@ std::vector<int> all_ids(int n) {
   std::vector<int> v(n);
   for (int i = 0; i < n; i++) v[i] = i;
   return v;
+}
+
+// One launch of cell stage `kind` over the domains `ids` (the same
+// workgroup grid per domain as its single-domain launch); fill(i, item)
+// sets domain i's stage arguments.
+template <class T, class Fill>
+ns_status stage_batched(ns_solver* s, int kind, const std::vector<int>& ids, Fill&& fill) {
+  const int n = (int)ids.size();
+  if (n == 0) return NS_OK;
+  StageItem* h = s->stage_h + (size_t)kind * s->in.size();
+  StageItem* d = s->stage_d + (size_t)kind * s->in.size();
+  int nb = 0;
+  for (int q = 0; q < n; q++) {
+    StageItem& it = h[q];
+    it = StageItem{};
+    it.g = s->in[ids[q]].g;
+    stage_item_grid(it, stage_target(kind));
+    it.first = nb;
+    nb += it.gx * it.gy * it.gz;
+    fill(ids[q], it);
+  }
+  HCK(s, hipMemcpyAsync(d, h, sizeof(StageItem) * n, hipMemcpyHostToDevice, s->stream));
+  HCK(s, launch_stage_batched<T>(s->stream, kind, d, n, nb));
+  return NS_OK;
+}
+
+// Largest wall speed per velocity component (the adaptive step's bound).
+void wall_speed_max(const ns_params& p, double wm[3]) {
+  for (int c = 0; c < 3; c++) wm[c] = 0.0;
+  for (int f = 0; f < 6; f++)
+    for (int c = 0; c < 3; c++) wm[c] = std::max(wm[c], std::fabs(p.wall_vel[f][c]));
 }
 
 // ---- batched solves ------------------------------------------------------------
@@ -1006,13 +1048,21 @@ ns_status solve_batched_mixed(ns_solver* s, std::vector<int>& sweeps, std::vecto
     sweeps[i] = 0;
     outer[i] = 0;
   }
-  ns_status e0 = fan_out(s, all_ids(n), false, [&](int i) {
-    Inst& I = s->in[i];
-    Timed t(s, NS_T_DEFECT, 0, 20LL * I.g.nx * I.g.ny * I.g.nz);
-    HCK(s, launch_defect(s->stream, I.g, I.s.p[I.s.pcur], nullptr, nullptr, (const float*)I.rhs, I.r, I.ctl,
-                         I.part, I.prm.eta));
-    return NS_OK;
-  });
+  long long cells_all = 0;
+  for (auto& I : s->in) cells_all += (long long)I.g.nx * I.g.ny * I.g.nz;
+  ns_status e0;
+  {
+    Timed t(s, NS_T_DEFECT, 0, 20LL * cells_all);
+    e0 = stage_batched<float>(s, kStageDefect, all_ids(n), [&](int i, StageItem& it) {
+      Inst& I = s->in[i];
+      it.in[0] = I.s.p[I.s.pcur];
+      it.in[2] = I.rhs;
+      it.out[1] = I.r;
+      it.ctl = I.ctl;
+      it.part = I.part;
+      it.s[0] = I.prm.eta;
+    });
+  }
   if (e0 != NS_OK) return e0;
   for (;;) {
     ns_status e = poll_all(s);
@@ -1036,18 +1086,30 @@ ns_status solve_batched_mixed(ns_solver* s, std::vector<int>& sweeps, std::vecto
     if (e != NS_OK) return e;
     std::vector<int> fb_of(n, 0);
     for (int q = 0; q < (int)ids.size(); q++) fb_of[ids[q]] = fbuf[q];
-    e = fan_out(s, ids, false, [&](int i) {
+    long long cells = 0;
+    for (int i : ids) {
       Inst& I = s->in[i];
       const int f = s->hctl[i].final_;
       sweeps[i] += f;
       I.pred = f;
-      Timed t(s, NS_T_DEFECT, 0, 40LL * I.g.nx * I.g.ny * I.g.nz);
-      HCK(s, launch_defect(s->stream, I.g, I.s.p[I.s.pcur], I.e[fb_of[i]], I.s.p[I.s.pcur ^ 1],
-                           (const float*)I.rhs, I.r, I.ctl, I.part, I.prm.eta));
-      I.s.pcur ^= 1;
-      return NS_OK;
-    });
+      cells += (long long)I.g.nx * I.g.ny * I.g.nz;
+    }
+    {
+      Timed t(s, NS_T_DEFECT, 0, 40LL * cells);
+      e = stage_batched<float>(s, kStageDefect, ids, [&](int i, StageItem& it) {
+        Inst& I = s->in[i];
+        it.in[0] = I.s.p[I.s.pcur];
+        it.in[1] = I.e[fb_of[i]];
+        it.in[2] = I.rhs;
+        it.out[0] = I.s.p[I.s.pcur ^ 1];
+        it.out[1] = I.r;
+        it.ctl = I.ctl;
+        it.part = I.part;
+        it.s[0] = I.prm.eta;
+      });
+    }
     if (e != NS_OK) return e;
+    for (int i : ids) s->in[i].s.pcur ^= 1;
   }
   return NS_OK;
 }
@@ -1056,14 +1118,98 @@ template <class T>
 ns_status step_batched(ns_solver* s) {
   const int n = (int)s->in.size();
   const std::vector<int> ids = all_ids(n);
-  ns_status e = fan_out(s, ids, false, [&](int i) { return step_pre<T>(s, i, s->in[i].s); });
+  std::vector<int> adapt;
+  for (int i = 0; i < n; i++)
+    if (s->in[i].prm.dt <= 0) adapt.push_back(i);
+  // The cell stages take one launch each for every domain (same arithmetic
+  // as the single-domain step); the face launches of the boundary fill go
+  // per domain to the library streams.
+  auto bc_fill = [&](int i) {
+    Inst& I = s->in[i];
+    Timed t(s, NS_T_BC);
+    HCK(s, launch_bc_vel<T>(s->stream, I.g, (T*)I.s.u, (T*)I.s.v, (T*)I.s.w, I.prm.wall_vel));
+    return NS_OK;
+  };
+  ns_status e = NS_OK;
+  if (!adapt.empty()) {
+    Timed t(s, NS_T_OTHER);
+    e = stage_batched<T>(s, kStageUmax, adapt, [&](int i, StageItem& it) {
+      Inst& I = s->in[i];
+      double wm[3];
+      wall_speed_max(I.prm, wm);
+      it.in[0] = I.s.u;
+      it.in[1] = I.s.v;
+      it.in[2] = I.s.w;
+      it.ctl = I.ctl;
+      it.part = I.part;
+      it.s[0] = I.prm.re;
+      it.s[1] = I.prm.tau;
+      for (int c = 0; c < 3; c++) it.s[2 + c] = wm[c];
+    });
+    if (e != NS_OK) return e;
+  }
+  e = fan_out(s, ids, false, bc_fill);
   if (e != NS_OK) return e;
+  {
+    Timed t(s, NS_T_FGH);
+    e = stage_batched<T>(s, kStageFgh, ids, [&](int i, StageItem& it) {
+      Inst& I = s->in[i];
+      it.in[0] = I.s.u;
+      it.in[1] = I.s.v;
+      it.in[2] = I.s.w;
+      for (int c = 0; c < 3; c++) it.in[3 + c] = I.frc[c];
+      it.out[0] = I.F;
+      it.out[1] = I.G;
+      it.out[2] = I.H;
+      it.ctl = I.ctl;
+      it.s[0] = 1.0 / I.prm.re;
+      it.s[1] = I.prm.gamma;
+      for (int c = 0; c < 3; c++) it.s[2 + c] = I.prm.g[c];
+    });
+    if (e != NS_OK) return e;
+  }
+  {
+    Timed t(s, NS_T_RHS);
+    e = stage_batched<T>(s, kStageRhs, ids, [&](int i, StageItem& it) {
+      Inst& I = s->in[i];
+      it.in[0] = I.F;
+      it.in[1] = I.G;
+      it.in[2] = I.H;
+      it.out[0] = I.rhs;
+      it.ctl = I.ctl;
+      it.part = I.part;
+      it.s[0] = I.prm.tol;
+    });
+    if (e != NS_OK) return e;
+  }
   std::vector<int> sweeps(n, 0), outer(n, 0);
   e = s->in[0].mixed ? solve_batched_mixed(s, sweeps, outer) : solve_batched_fp64(s, sweeps);
   if (e != NS_OK) return e;
-  const ns_status ret = fan_out(s, ids, true, [&](int i) {
-    return step_post<T>(s, i, s->in[i].s, sweeps[i], outer[i], true);
+  ns_status ret = fan_out(s, ids, true, [&](int i) {
+    Inst& I = s->in[i];
+    Timed t(s, NS_T_PROJECT);
+    HCK(s, launch_p_ghosts<double>(s->stream, I.g, I.s.p[I.s.pcur]));
+    return NS_OK;
   });
+  if (ret == NS_OK) {
+    Timed t(s, NS_T_PROJECT);
+    ret = stage_batched<T>(s, kStageProject, ids, [&](int i, StageItem& it) {
+      Inst& I = s->in[i];
+      it.in[0] = I.F;
+      it.in[1] = I.G;
+      it.in[2] = I.H;
+      it.in[3] = I.s.p[I.s.pcur];
+      it.out[0] = I.s.u;
+      it.out[1] = I.s.v;
+      it.out[2] = I.s.w;
+      it.ctl = I.ctl;
+    });
+  }
+  if (ret == NS_OK) ret = fan_out(s, ids, true, bc_fill);
+  for (int i : ids) {
+    const ns_status a = step_account(s, i, sweeps[i], outer[i], true);
+    if (a != NS_OK && ret == NS_OK) ret = a;
+  }
   if (s->timing) {
     HCK(s, hipStreamSynchronize(s->stream));
     harvest(s, 1 << 30);
@@ -1229,7 +1375,10 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
     // room for a full table and a table of re-sweeps behind it
     if (hipHostMalloc((void**)&s->items_h, 2 * sizeof(BatchItem) * n_instances, hipHostMallocDefault) !=
             hipSuccess ||
-        hipMalloc((void**)&s->items_d, 2 * sizeof(BatchItem) * n_instances) != hipSuccess)
+        hipMalloc((void**)&s->items_d, 2 * sizeof(BatchItem) * n_instances) != hipSuccess ||
+        hipHostMalloc((void**)&s->stage_h, sizeof(StageItem) * kStageKinds * n_instances, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipMalloc((void**)&s->stage_d, sizeof(StageItem) * kStageKinds * n_instances) != hipSuccess)
       return bail(NS_E_OOM, "batch table allocation failed");
     if (params[0].tile[0] > 0) {
       s->batch_ty = params[0].tile[0];
@@ -1475,6 +1624,8 @@ void ns_destroy(ns_solver* s) {
   if (s->hctl) (void)hipHostFree(s->hctl);
   if (s->items_h) (void)hipHostFree(s->items_h);
   (void)hipFree(s->items_d);
+  if (s->stage_h) (void)hipHostFree(s->stage_h);
+  (void)hipFree(s->stage_d);
   for (int k = 0; k < ns_solver::kAux; k++) {
     if (s->aux[k]) (void)hipStreamDestroy(s->aux[k]);
     if (s->ev_join[k]) (void)hipEventDestroy(s->ev_join[k]);

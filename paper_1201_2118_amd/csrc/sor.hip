@@ -144,21 +144,20 @@ k_sor_black(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
 // Mixed-precision outer step: p_out = p_in + e, r = rhs - A p_out (FP64
 // arithmetic, stored as FP32), RMS of the FP64 r into ctl->res; decides
 // outer convergence and sets the inner threshold eta * RMS(r).
-__global__ void __launch_bounds__(kBlock)
-k_defect(int zr, const double* __restrict__ p_in, const float* __restrict__ e, double* __restrict__ p_out,
-         const float* __restrict__ rhs, float* __restrict__ r, Geo g, Ctl* ctl, double* part,
-         double eta) {
-  __shared__ double sh[16];
-  __shared__ int sh_last;
+__device__ __forceinline__ void defect_cells(const Geo& g, int zr, const CellBlk& blk,
+                                             const double* __restrict__ p_in, const float* __restrict__ e,
+                                             double* __restrict__ p_out, const float* __restrict__ rhs,
+                                             float* __restrict__ r, Ctl* ctl, double* part, double eta, double* sh,
+                                             int* sh_last) {
   const long n = (long)g.nx * g.ny * g.nz;
   double acc = 0.0;
   // A thread marches its (i, j) column through a run of zr planes and keeps
   // p + e of the planes below, at and above the cell in registers.
-  const int i = blockIdx.x * kCellX + threadIdx.x + 1;
-  const int j = blockIdx.y * kCellY + threadIdx.y + 1;
+  const int i = blk.x * kCellX + threadIdx.x + 1;
+  const int j = blk.y * kCellY + threadIdx.y + 1;
   if (i <= g.nx && j <= g.ny) {
     const Nb nb = neighbours(g, i, j, 1);  // x and y entries; z per plane below
-    const int k0 = blockIdx.z * zr + 1;
+    const int k0 = blk.z * zr + 1;
     const int k1 = min(g.nz, k0 + zr - 1);
     auto q = [&](long c) { return p_in[c] + (e ? (double)e[c] : 0.0); };
     const int per2 = g.per[2];
@@ -183,11 +182,9 @@ k_defect(int zr, const double* __restrict__ p_in, const float* __restrict__ e, d
       qc = qu;
     }
   }
-  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  const unsigned nbk = gridDim.x * gridDim.y * gridDim.z;
   double s = block_sum(acc, sh);
-  if (publish_partial(part, bid, s, ctl, nbk, &sh_last)) {
-    double tot = sum_partials(part, nbk, sh);
+  if (publish_partial(part, blk.id, s, ctl, blk.count, sh_last)) {
+    double tot = sum_partials(part, blk.count, sh);
     if (flat_tid() == 0) {
       // an identically zero rhs needs no correction at all
       const double res = ctl->rhs_rms == 0.0 ? 0.0 : sqrt(tot / (double)n);
@@ -201,6 +198,38 @@ k_defect(int zr, const double* __restrict__ p_in, const float* __restrict__ e, d
       ctl->ticket = 0;
     }
   }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_defect(int zr, const double* __restrict__ p_in, const float* __restrict__ e, double* __restrict__ p_out,
+         const float* __restrict__ rhs, float* __restrict__ r, Geo g, Ctl* ctl, double* part,
+         double eta) {
+  __shared__ double sh[16];
+  __shared__ int sh_last;
+  defect_cells(g, zr, own_blk(), p_in, e, p_out, rhs, r, ctl, part, eta, sh, &sh_last);
+}
+
+// Every domain of a batch in one launch (workgroup -> domain as for the
+// other batched stages).
+__global__ void __launch_bounds__(kBlock) k_defect_batched(const StageItem* __restrict__ items, int nitems) {
+  __shared__ double sh[16];
+  __shared__ int sh_last;
+  const int b = blockIdx.x;
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= b) lo = mid; else hi = mid - 1;
+  }
+  const StageItem& it = items[lo];
+  const int l = b - it.first;
+  CellBlk blk;
+  blk.x = l % it.gx;
+  blk.y = (l / it.gx) % it.gy;
+  blk.z = l / (it.gx * it.gy);
+  blk.id = (unsigned)l;
+  blk.count = (unsigned)(it.gx * it.gy * it.gz);
+  defect_cells(it.g, it.zr, blk, (const double*)it.in[0], (const float*)it.in[1], (double*)it.out[0],
+               (const float*)it.in[2], (float*)it.out[1], it.ctl, it.part, it.s[0], sh, &sh_last);
 }
 
 }  // namespace
@@ -231,6 +260,11 @@ hipError_t launch_defect(hipStream_t st, const Geo& g, const double* p_in, const
                          double eta) {
   const long n = (long)g.nx * g.ny * g.nz;
   k_defect<<<cell_grid(g, kRedDefect), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, kRedDefect), p_in, e, p_out, rhs, r, g, ctl, part, eta);
+  return hipGetLastError();
+}
+
+hipError_t launch_defect_batched(hipStream_t st, const StageItem* d_items, int nitems, int nblocks) {
+  k_defect_batched<<<nblocks, dim3(kCellX, kCellY), 0, st>>>(d_items, nitems);
   return hipGetLastError();
 }
 
