@@ -231,21 +231,22 @@ struct StageItem {
   double* part;
   double s[6];
 };
-// Host: workgroup grid of a domain for a stage (target = reduction
-// workgroups as for the single-domain launch, 0 without a reduction).
-inline void stage_item_grid(StageItem& it, long target) {
-  const dim3 d = cell_grid(it.g, target);
+// Host: workgroup grid of a domain for a batched stage: whole z columns for
+// a reducing stage, the single-domain grid otherwise.
+inline void stage_item_grid(StageItem& it, bool whole_columns) {
+  const dim3 d = cell_grid(it.g, 0);
   it.gx = (int)d.x;
   it.gy = (int)d.y;
-  it.gz = (int)d.z;
-  it.zr = cell_zrun(it.g, target);
+  it.gz = whole_columns ? 1 : (int)d.z;
+  it.zr = whole_columns ? it.g.nz : cell_zrun(it.g, 0);
 }
 enum StageKind { kStageFgh = 0, kStageRhs, kStageProject, kStageUmax, kStageDefect, kStageKinds };
-// Workgroups per domain of each stage: the same grids as the single-domain
-// launchers.
-inline long stage_target(int kind) {
-  return kind == kStageRhs || kind == kStageUmax ? kRedRhs : (kind == kStageDefect ? kRedDefect : 0);
-}
+// Stages that end in a reduction over the domain.  Every workgroup of such
+// a stage publishes its partial behind a device-scope fence, whose cost does
+// not shrink with the workgroup's share of the work; a batched launch
+// therefore gives each workgroup of these stages a whole z column (the
+// other stages keep the single-domain grid).
+inline bool stage_reduces(int kind) { return kind == kStageRhs || kind == kStageUmax || kind == kStageDefect; }
 // One launch of a stage over nitems domains (nblocks = sum of their
 // workgroups), the same per-cell arithmetic as the single-domain kernels.
 //   kStageFgh:     in = u, v, w, fx, fy, fz; out = F, G, H; s = nu, gamma, gx, gy, gz (dt from ctl)

@@ -821,7 +821,7 @@ ns_status stage_batched(ns_solver* s, int kind, const std::vector<int>& ids, Fil
     StageItem& it = h[q];
     it = StageItem{};
     it.g = s->in[ids[q]].g;
-    stage_item_grid(it, stage_target(kind));
+    stage_item_grid(it, stage_reduces(kind));
     it.first = nb;
     nb += it.gx * it.gy * it.gz;
     fill(ids[q], it);
