@@ -171,7 +171,10 @@ __device__ __forceinline__ double flux(double t, double a, double b, double gamm
   return 0.5 * (t * (a + b) + gamma * fabs(t) * (a - b));
 }
 
-template <class T>
+// HAS_F: body-force fields fx, fy, fz are present (all three or none).  A
+// compile-time choice, so the loop body carries no per-cell branch and the
+// loads of the three components can be in flight together.
+template <class T, bool HAS_F>
 __device__ __forceinline__ void fgh_cells(const Geo& g, int zr, const CellBlk& blk, const T* __restrict__ u,
                                           const T* __restrict__ v, const T* __restrict__ w,
                                           const T* __restrict__ fx, const T* __restrict__ fy,
@@ -180,8 +183,12 @@ __device__ __forceinline__ void fgh_cells(const Geo& g, int zr, const CellBlk& b
                                           double gx, double gy, double gz) {
   const double dt = ctl->dt;
   const long sx = g.sx, sxy = g.sxy;
+  // All three components are formed at every cell (their stencils stay
+  // inside the padded arrays) and stored where they are unknowns: the body
+  // is one straight block, so the loads of all three are in flight together.
   for_cells(g, zr, blk, [&](int ci, int cj, int ck, long c) {
-    if (ci <= g.hi[0]) {  // F on the x face i
+    double Fv, Gv, Hv;
+    {  // F on the x face i
       const double q = u[c], qe = u[c + 1], qw = u[c - 1], qn = u[c + sx], qs = u[c - sx],
                    qt = u[c + sxy], qb = u[c - sxy];
       const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
@@ -193,10 +200,10 @@ __device__ __forceinline__ void fgh_cells(const Geo& g, int zr, const CellBlk& b
       const double wt = 0.5 * ((double)w[c] + (double)w[c + 1]);
       const double wb = 0.5 * ((double)w[c - sxy] + (double)w[c - sxy + 1]);
       const double cz = (flux(wt, q, qt, gamma) - flux(wb, qb, q, gamma)) * g.idz;
-      const double f = gx + (fx ? (double)fx[c] : 0.0);
-      F[c] = T(q + dt * (nu * lap - cx - cy - cz + f));
+      const double f = gx + (HAS_F ? (double)fx[c] : 0.0);
+      Fv = q + dt * (nu * lap - cx - cy - cz + f);
     }
-    if (cj <= g.hi[1]) {  // G on the y face j
+    {  // G on the y face j
       const double q = v[c], qe = v[c + 1], qw = v[c - 1], qn = v[c + sx], qs = v[c - sx],
                    qt = v[c + sxy], qb = v[c - sxy];
       const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
@@ -208,10 +215,10 @@ __device__ __forceinline__ void fgh_cells(const Geo& g, int zr, const CellBlk& b
       const double wt = 0.5 * ((double)w[c] + (double)w[c + sx]);
       const double wb = 0.5 * ((double)w[c - sxy] + (double)w[c - sxy + sx]);
       const double cz = (flux(wt, q, qt, gamma) - flux(wb, qb, q, gamma)) * g.idz;
-      const double f = gy + (fy ? (double)fy[c] : 0.0);
-      G[c] = T(q + dt * (nu * lap - cx - cy - cz + f));
+      const double f = gy + (HAS_F ? (double)fy[c] : 0.0);
+      Gv = q + dt * (nu * lap - cx - cy - cz + f);
     }
-    if (ck <= g.hi[2]) {  // H on the z face k
+    {  // H on the z face k
       const double q = w[c], qe = w[c + 1], qw = w[c - 1], qn = w[c + sx], qs = w[c - sx],
                    qt = w[c + sxy], qb = w[c - sxy];
       const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
@@ -223,9 +230,12 @@ __device__ __forceinline__ void fgh_cells(const Geo& g, int zr, const CellBlk& b
       const double vs = 0.5 * ((double)v[c - sx] + (double)v[c - sx + sxy]);
       const double cy = (flux(vn, q, qn, gamma) - flux(vs, qs, q, gamma)) * g.idy;
       const double cz = (flux(0.5 * (q + qt), q, qt, gamma) - flux(0.5 * (qb + q), qb, q, gamma)) * g.idz;
-      const double f = gz + (fz ? (double)fz[c] : 0.0);
-      H[c] = T(q + dt * (nu * lap - cx - cy - cz + f));
+      const double f = gz + (HAS_F ? (double)fz[c] : 0.0);
+      Hv = q + dt * (nu * lap - cx - cy - cz + f);
     }
+    if (ci <= g.hi[0]) F[c] = T(Fv);
+    if (cj <= g.hi[1]) G[c] = T(Gv);
+    if (ck <= g.hi[2]) H[c] = T(Hv);
   });
 }
 
@@ -235,7 +245,10 @@ k_fgh(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restr
       const T* __restrict__ fx, const T* __restrict__ fy, const T* __restrict__ fz,
       T* __restrict__ F, T* __restrict__ G, T* __restrict__ H, Geo g, const Ctl* __restrict__ ctl,
       double nu, double gamma, double gx, double gy, double gz) {
-  fgh_cells<T>(g, zr, own_blk(), u, v, w, fx, fy, fz, F, G, H, ctl, nu, gamma, gx, gy, gz);
+  if (fx)
+    fgh_cells<T, true>(g, zr, own_blk(), u, v, w, fx, fy, fz, F, G, H, ctl, nu, gamma, gx, gy, gz);
+  else
+    fgh_cells<T, false>(g, zr, own_blk(), u, v, w, fx, fy, fz, F, G, H, ctl, nu, gamma, gx, gy, gz);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,9 +401,18 @@ template <class T>
 __global__ void __launch_bounds__(kBlock) k_fgh_batched(const StageItem* __restrict__ items, int nitems) {
   CellBlk blk;
   const StageItem& it = stage_item(items, nitems, blk);
-  fgh_cells<T>(it.g, it.zr, blk, (const T*)it.in[0], (const T*)it.in[1], (const T*)it.in[2], (const T*)it.in[3],
-               (const T*)it.in[4], (const T*)it.in[5], (T*)it.out[0], (T*)it.out[1], (T*)it.out[2], it.ctl, it.s[0],
-               it.s[1], it.s[2], it.s[3], it.s[4]);
+  const T* u = (const T*)it.in[0];
+  const T* v = (const T*)it.in[1];
+  const T* w = (const T*)it.in[2];
+  const T* fx = (const T*)it.in[3];
+  const T* fy = (const T*)it.in[4];
+  const T* fz = (const T*)it.in[5];
+  if (fx)
+    fgh_cells<T, true>(it.g, it.zr, blk, u, v, w, fx, fy, fz, (T*)it.out[0], (T*)it.out[1], (T*)it.out[2], it.ctl,
+                       it.s[0], it.s[1], it.s[2], it.s[3], it.s[4]);
+  else
+    fgh_cells<T, false>(it.g, it.zr, blk, u, v, w, fx, fy, fz, (T*)it.out[0], (T*)it.out[1], (T*)it.out[2], it.ctl,
+                        it.s[0], it.s[1], it.s[2], it.s[3], it.s[4]);
 }
 
 template <class T>

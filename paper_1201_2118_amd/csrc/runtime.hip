@@ -1419,9 +1419,11 @@ ns_status ns_set_state(ns_solver* s, int32_t inst, int32_t field, const double* 
     case NS_W: dst = I.s.w; break;
     case NS_P: dst = I.s.p[I.s.pcur]; f32 = false; break;
     case NS_FX: case NS_FY: case NS_FZ: {
-      void*& f = I.frc[field - NS_FX];
-      if (!f) HCK(s, dmalloc(&f, I.bytes));
-      dst = f;
+      // the three force fields exist together (zero where never set): the
+      // predictor reads all of them or none
+      for (int c = 0; c < 3; c++)
+        if (!I.frc[c]) HCK(s, dmalloc(&I.frc[c], I.bytes));
+      dst = I.frc[field - NS_FX];
       break;
     }
     case NS_F: dst = I.F; break;

@@ -144,6 +144,10 @@ k_sor_black(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
 // Mixed-precision outer step: p_out = p_in + e, r = rhs - A p_out (FP64
 // arithmetic, stored as FP32), RMS of the FP64 r into ctl->res; decides
 // outer convergence and sets the inner threshold eta * RMS(r).
+// HAS_E: p_out = p_in + e is formed and stored (e non-null); else p = p_in.
+// A compile-time choice, so the loop body carries no per-load branch and
+// its loads can be in flight together.
+template <bool HAS_E>
 __device__ __forceinline__ void defect_cells(const Geo& g, int zr, const CellBlk& blk,
                                              const double* __restrict__ p_in, const float* __restrict__ e,
                                              double* __restrict__ p_out, const float* __restrict__ rhs,
@@ -159,12 +163,20 @@ __device__ __forceinline__ void defect_cells(const Geo& g, int zr, const CellBlk
     const Nb nb = neighbours(g, i, j, 1);  // x and y entries; z per plane below
     const int k0 = blk.z * zr + 1;
     const int k1 = min(g.nz, k0 + zr - 1);
-    auto q = [&](long c) { return p_in[c] + (e ? (double)e[c] : 0.0); };
+    auto q = [&](long c) {
+      if constexpr (HAS_E)
+        return p_in[c] + (double)e[c];
+      else
+        return p_in[c] + 0.0;
+    };
     const int per2 = g.per[2];
     auto zdn = [&](int k) -> long { return k > 1 ? -g.sxy : (per2 ? (long)(g.nz - 1) * g.sxy : 0L); };
     auto zup = [&](int k) -> long { return k < g.nz ? g.sxy : (per2 ? -(long)(g.nz - 1) * g.sxy : 0L); };
     long c = (long)k0 * g.sxy + (long)j * g.sx + i;
     double qc = q(c), qd = q(c + zdn(k0));
+    // two planes per trip: the loads of the second are issued with those of
+    // the first (measured 5 % faster than one, and faster than four)
+#pragma unroll 2
     for (int k = k0; k <= k1; k++, c += g.sxy) {
       const double qu = q(c + zup(k));
       const double azm = (k > 1 || per2) ? g.idz2 : 0.0;
@@ -177,7 +189,7 @@ __device__ __forceinline__ void defect_cells(const Geo& g, int zr, const CellBlk
       const double rr = (double)rhs[c] - s;
       r[c] = (float)rr;
       acc += rr * rr;
-      if (e) p_out[c] = qc;
+      if constexpr (HAS_E) p_out[c] = qc;
       qd = qc;
       qc = qu;
     }
@@ -206,7 +218,10 @@ k_defect(int zr, const double* __restrict__ p_in, const float* __restrict__ e, d
          double eta) {
   __shared__ double sh[16];
   __shared__ int sh_last;
-  defect_cells(g, zr, own_blk(), p_in, e, p_out, rhs, r, ctl, part, eta, sh, &sh_last);
+  if (e)
+    defect_cells<true>(g, zr, own_blk(), p_in, e, p_out, rhs, r, ctl, part, eta, sh, &sh_last);
+  else
+    defect_cells<false>(g, zr, own_blk(), p_in, e, p_out, rhs, r, ctl, part, eta, sh, &sh_last);
 }
 
 // Every domain of a batch in one launch (workgroup -> domain as for the
@@ -228,8 +243,15 @@ __global__ void __launch_bounds__(kBlock) k_defect_batched(const StageItem* __re
   blk.z = l / (it.gx * it.gy);
   blk.id = (unsigned)l;
   blk.count = (unsigned)(it.gx * it.gy * it.gz);
-  defect_cells(it.g, it.zr, blk, (const double*)it.in[0], (const float*)it.in[1], (double*)it.out[0],
-               (const float*)it.in[2], (float*)it.out[1], it.ctl, it.part, it.s[0], sh, &sh_last);
+  const double* p_in = (const double*)it.in[0];
+  const float* e = (const float*)it.in[1];
+  const float* rhs = (const float*)it.in[2];
+  if (e)
+    defect_cells<true>(it.g, it.zr, blk, p_in, e, (double*)it.out[0], rhs, (float*)it.out[1], it.ctl, it.part,
+                       it.s[0], sh, &sh_last);
+  else
+    defect_cells<false>(it.g, it.zr, blk, p_in, e, (double*)it.out[0], rhs, (float*)it.out[1], it.ctl, it.part,
+                        it.s[0], sh, &sh_last);
 }
 
 }  // namespace
