@@ -269,7 +269,9 @@ ns_status tune_run(ns_solver* s, Inst& I, Ctl* tctl, const SorShape& sh, float* 
   T* out = (T*)(I.mixed ? (void*)I.e[1] : (void*)I.s.p[1]);
   const T* rhs = (const T*)(I.mixed ? (void*)I.r : I.rhs);
   hipError_t e = hipSuccess;
-  for (int it = 0; it < 4 && e == hipSuccess; it++) {
+  // one warm-up launch, then eight timed (the shapes of a batch lie within a
+  // few per cent of each other, so fewer launches let noise pick)
+  for (int it = 0; it < 9 && e == hipSuccess; it++) {
     if (it == 1) e = hipEventRecord(a, s->stream);
     // sweep index 1 (pass: 0): no residual of these launches is a stop decision
     if (e == hipSuccess)
@@ -386,7 +388,9 @@ ns_status tune_batch_run(ns_solver* s, Ctl* tctl, int ty, int zc, float* ms) {
   HCK(s, hipEventCreate(&a));
   HCK(s, hipEventCreate(&b));
   hipError_t e = hipSuccess;
-  for (int it = 0; it < 4 && e == hipSuccess; it++) {
+  // one warm-up launch, then eight timed (the shapes of a batch lie within a
+  // few per cent of each other, so fewer launches let noise pick)
+  for (int it = 0; it < 9 && e == hipSuccess; it++) {
     if (it == 1) e = hipEventRecord(a, s->stream);
     // sweep index 1 (pass: 0): no residual of these launches is a stop decision
     if (e == hipSuccess)
