@@ -49,11 +49,14 @@ constexpr int kLanes = 64;  // x positions per row (one wave)
 constexpr int kR24 = 2, kR32 = 2;  // 3 rows on 8 waves and 4 rows on 8 waves ran slower at 512^3
 // Planes per register ring (input and rhs) = steps per unrolled trip: a
 // plane is loaded ring - 2 steps before the step that first reads it.  Six
-// planes (loads four steps ahead) where the registers allow it at the
-// workgroup's occupancy: FP32 with 12 waves; four elsewhere.
+// planes (loads four steps ahead) for FP32 with 12 or 16 waves; four
+// elsewhere.  With 16 waves the six-plane rings need 5 more registers than
+// the 128 of that occupancy: the compiler keeps 5 values in scratch, which
+// still runs 5 % faster per step than loading two steps ahead (the loads'
+// latency is the larger cost).
 template <class T, int R, int W>
 constexpr int ring_of() {
-  return sizeof(T) == 4 && W == 12 && R == 2 ? 6 : 4;
+  return sizeof(T) == 4 && W >= 12 && R == 2 ? 6 : 4;
 }
 
 __device__ __forceinline__ int dpp_left(int v) {  // lane l receives lane l - 1 (0 at lane 0)
@@ -169,9 +172,12 @@ __device__ __forceinline__ void st_plane(const Plane& b, unsigned& off, T v) {
 }
 
 // LDS edge rows: per quantity and step parity, two rows (top, bottom) per
-// wave.
+// wave, between a padding row before the first wave's and one after the
+// last wave's (zero, never written: the rows beyond the workgroup's ends,
+// whose values only reach halo rows), so every wave finds the rows above
+// and below its own at fixed offsets from one address.
 template <int W>
-constexpr int kEdge = W * 2 * kLanes;
+constexpr int kEdge = (W * 2 + 2) * kLanes;
 
 template <class T, int NS, int R, int W, bool ZIN>
 __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restrict__ p_out,
@@ -205,6 +211,23 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   T ownf[R];
 #pragma unroll
   for (int r = 0; r < R; r++) ownf[r] = owny(r) && ownx ? T(1) : T(0);
+  // FP32 applies the same ownership as a lane mask per row held in scalar
+  // registers, with one v_cndmask (no vector register for the factor; the
+  // compiler would split the compound condition into several selects)
+  unsigned long long ownm[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) ownm[r] = owny(r) ? __builtin_amdgcn_ballot_w64(ownx) : 0ull;
+  // the residual of row r's cell where it counts (and the plane lies in the
+  // chunk), 0 elsewhere
+  auto counted = [&](T res, int r, bool chunk) -> T {
+    if constexpr (sizeof(T) == 4) {
+      float out;
+      asm("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(out) : "v"(res), "s"(chunk ? ownm[r] : 0ull));
+      return out;
+    } else {
+      return res * (chunk ? ownf[r] : T(0));
+    }
+  };
   // diagonal a_c and relaxation factor omega / a_c of row r's cell with both
   // z neighbours (d2, w2) or one (d1, w1, planes next to a z wall)
   auto dxy_of = [&](int j) -> double {
@@ -250,12 +273,12 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   for (int r = 0; r < R; r++)
     off[r] = (unsigned)((long)wrap_clamp(j0 + r, g.ny, per1) * g.sx + iw) * (unsigned)sizeof(T);
 
-  // LDS: this wave's top / bottom rows, and the rows above / below it (its
-  // own edge row at the workgroup's ends, where the value is never used)
-  const int e_top = (wy * 2) * kLanes + tx;
+  // LDS: this wave's top / bottom rows, and the rows above / below it (the
+  // padding rows at the workgroup's ends)
+  const int e_top = (wy * 2 + 1) * kLanes + tx;
   const int e_bot = e_top + kLanes;
-  const int e_above = wy > 0 ? e_top - kLanes : e_top;
-  const int e_below = wy < W - 1 ? e_bot + kLanes : e_bot;
+  const int e_above = e_top - kLanes;
+  const int e_below = e_bot + kLanes;
   auto ebuf = [&](int q, int par) -> T* { return E + (q * 2 + par) * kEdge<W>; };
 
   auto plane_of = [&](int k) -> long {
@@ -331,7 +354,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
         const T res = stencil(pc, ps, pn, pm2[r], p0[r], axm, axp, aym(j0 + r),
                               ayp(j0 + r), azm, azp, dg) -
                       qm1[r];
-        acc1 = add_sq(res * (IN || in_chunk ? ownf[r] : T(0)), acc1);
+        acc1 = add_sq(counted(res, r, IN || in_chunk), acc1);
         X1n[r] = fmaT(wg, res, pc);
       }
     }
@@ -382,7 +405,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
           const T res = stencil(pc, ps, pn, Ma[r], Mn[r], axm, axp, aym(j0 + r),
                                 ayp(j0 + r), azm, azp, dg) -
                         hC[r];
-          acc2 = add_sq(res * (IN || in_chunk ? ownf[r] : T(0)), acc2);
+          acc2 = add_sq(counted(res, r, IN || in_chunk), acc2);
           X2n[r] = fmaT(wg, res, pc);
         }
       }
