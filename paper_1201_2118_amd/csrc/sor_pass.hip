@@ -54,9 +54,13 @@ constexpr int kR24 = 2, kR32 = 2;  // 3 rows on 8 waves and 4 rows on 8 waves ra
 // the 128 of that occupancy: the compiler keeps 5 values in scratch, which
 // still runs 5 % faster per step than loading two steps ahead (the loads'
 // latency is the larger cost).
-template <class T, int R, int W>
+#ifndef NS_RING_D8
+#define NS_RING_D8 6
+#endif
+template <class T, int R, int W, bool BATCH>
 constexpr int ring_of() {
-  return sizeof(T) == 4 && W >= 12 && R == 2 ? 6 : 4;
+  if constexpr (sizeof(T) == 8) return BATCH ? 4 : NS_RING_D8;
+  return W >= 12 && R == 2 ? 6 : 4;
 }
 
 __device__ __forceinline__ int dpp_left(int v) {  // lane l receives lane l - 1 (0 at lane 0)
@@ -179,7 +183,7 @@ __device__ __forceinline__ void st_plane(const Plane& b, unsigned& off, T v) {
 template <int W>
 constexpr int kEdge = (W * 2 + 2) * kLanes;
 
-template <class T, int NS, int R, int W, bool ZIN>
+template <class T, int NS, int R, int W, bool ZIN, bool BATCH>
 __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restrict__ p_out,
                                           const T* __restrict__ rhs, const Geo& g, double omega, int write,
                                           int col, int z0, int z1, int ntx, T* __restrict__ E, double& acc1,
@@ -187,7 +191,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
   constexpr int H = 2 * NS;
   constexpr int TX = kLanes - 2 * H;
   constexpr int ROWS = R * W;
-  constexpr int kRing = ring_of<T, R, W>();
+  constexpr int kRing = ring_of<T, R, W, BATCH>();
   constexpr int TY = ROWS - 2 * H;
   const int tx = threadIdx.x;
   const int wy = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
@@ -575,7 +579,7 @@ k_sor_pass(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restric
     for (int tile = li; tile < ntiles; tile += G) {
       const int col = tile % ncols, bz = tile / ncols;
       const int z0 = 1 + bz * zc;
-      pass_tile<T, NS, R, W, ZIN>(p_in, p_out, rhs, g, omega, write, col, z0, min(g.nz, z0 + zc - 1), ntx, E,
+      pass_tile<T, NS, R, W, ZIN, false>(p_in, p_out, rhs, g, omega, write, col, z0, min(g.nz, z0 + zc - 1), ntx, E,
                                   acc1, acc2);
       __syncthreads();
     }
@@ -589,7 +593,7 @@ k_sor_pass(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restric
       const int col = (int)(q0 / g.nz);
       const int z0 = (int)(q0 - (long)col * g.nz) + 1;
       const int z1 = (int)min((long)g.nz, (long)z0 + (q1 - q0) - 1);
-      pass_tile<T, NS, R, W, ZIN>(p_in, p_out, rhs, g, omega, write, col, z0, z1, ntx, E, acc1,
+      pass_tile<T, NS, R, W, ZIN, false>(p_in, p_out, rhs, g, omega, write, col, z0, z1, ntx, E, acc1,
                                   acc2);
       __syncthreads();
       q0 += z1 - z0 + 1;
@@ -638,7 +642,7 @@ k_pass_batched(const BatchItem* __restrict__ items, int nitems, int m, int q, in
   const int z0 = 1 + bz * it.zc;
   const int in = (it.cur + q) & 1;
   double acc1 = 0.0, acc2 = 0.0;
-  pass_tile<T, NS, R, W, ZIN>((const T*)it.p[in], (T*)it.p[in ^ 1], (const T*)it.rhs, g, it.omega, 1, col, z0,
+  pass_tile<T, NS, R, W, ZIN, true>((const T*)it.p[in], (T*)it.p[in ^ 1], (const T*)it.rhs, g, it.omega, 1, col, z0,
                               min(g.nz, z0 + it.zc - 1), it.ntx, E, acc1, acc2);
   __syncthreads();
   if (force) return;
