@@ -49,18 +49,20 @@ constexpr int kLanes = 64;  // x positions per row (one wave)
 constexpr int kR24 = 2, kR32 = 2;  // 3 rows on 8 waves and 4 rows on 8 waves ran slower at 512^3
 // Planes per register ring (input and rhs) = steps per unrolled trip: a
 // plane is loaded ring - 2 steps before the step that first reads it.  Six
-// planes (loads four steps ahead) for FP32 with 12 or 16 waves; four
-// elsewhere.  With 16 waves the six-plane rings need 5 more registers than
-// the 128 of that occupancy: the compiler keeps 5 values in scratch, which
-// still runs 5 % faster per step than loading two steps ahead (the loads'
-// latency is the larger cost).
-#ifndef NS_RING_D8
-#define NS_RING_D8 6
-#endif
+// planes (loads four steps ahead) for the single-domain kernel's FP64 tiles
+// and 12- and 16-wave FP32 tiles and for the batched kernel's 12-wave FP32
+// tiles; four for the rest (8-wave FP32 tiles would drop from two
+// workgroups per CU to one, the other batched tiles would spill).  FP32 tiles of 16
+// waves need 5 more registers than the 128 of their occupancy: the compiler
+// keeps 5 values in scratch, and the tile still runs 5 % faster than with
+// loads two steps ahead (the loads' latency is the larger cost).  Eight
+// planes measured: FP64 2 % faster but spilling, FP32 16-wave tiles much
+// slower (24 values in scratch).
 template <class T, int R, int W, bool BATCH>
 constexpr int ring_of() {
-  if constexpr (sizeof(T) == 8) return BATCH ? 4 : NS_RING_D8;
-  return W >= 12 && R == 2 ? 6 : 4;
+  if constexpr (R != 2) return 4;
+  if constexpr (BATCH) return sizeof(T) == 4 && W == 12 ? 6 : 4;
+  return sizeof(T) == 8 || W >= 12 ? 6 : 4;
 }
 
 __device__ __forceinline__ int dpp_left(int v) {  // lane l receives lane l - 1 (0 at lane 0)
