@@ -270,7 +270,7 @@ def main():
             "sweeps_per_launch": per_launch,
             "bytes_per_launch": dom["sor_bytes_per_launch"], "avg_launch_ms": round(dom["sor_avg_ms"], 5),
             "sweep_equivalent_gbs": round(per_launch * dom["sor_gbs"], 1),
-            "limiter": ("instruction issue and waits: VALU 61% busy, half of the wave cycles waiting on "
+            "limiter": ("instruction issue and waits: VALU 64% busy, 45% of the wave cycles waiting on "
                         "memory / LDS / the per-plane barrier (SQ counters)") if per_launch == 2 and f32
                        else ("vector-ALU issue (two sweeps per launch)" if per_launch == 2 else "HBM"),
             "tile": dom["tile"]}
