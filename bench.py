@@ -41,23 +41,34 @@ def log(msg):
 
 
 def measure(prm, steps, warmup):
+    """Throughput of K steps on a handle without stage timers (HIP events
+    around every launch would add their own gaps to the step), then the
+    per-stage and per-launch figures from a second handle of the same grid
+    with NS_TIMING (same sweep shape: the autotuner caches it per grid)."""
     import torch
 
     from paper_1201_2118_amd import abi
     from paper_1201_2118_amd.solver import Solver
 
-    prm = dict(prm, flags=abi.NS_TIMING)
-    s = Solver(prm, device="cuda:0")
+    s = Solver(dict(prm, flags=0), device="cuda:0")
     if warmup:
         s.step(warmup)
-    t0 = s.timing()
     torch.cuda.synchronize()
     a = time.perf_counter()
     s.step(steps)
     torch.cuda.synchronize()
     b = time.perf_counter()
-    t1 = s.timing()
     st = s.stats()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+
+    tsteps = min(steps, 2)
+    s = Solver(dict(prm, flags=abi.NS_TIMING), device="cuda:0")
+    s.step(1)
+    t0 = s.timing()
+    s.step(tsteps)
+    t1 = s.timing()
     tile = [t1.sor_tile[0], t1.sor_tile[1]]
     s.close()
     n = prm["nx"] * prm["ny"] * prm["nz"]
@@ -65,7 +76,7 @@ def measure(prm, steps, warmup):
     sor_ms = t1.ms[abi.NS_T_SOR] - t0.ms[abi.NS_T_SOR]
     sor_launches = t1.launches[abi.NS_T_SOR] - t0.launches[abi.NS_T_SOR]
     sor_bytes = t1.sor_bytes - t0.sor_bytes
-    stage_ms = {name: (t1.ms[i] - t0.ms[i]) / steps for name, i in
+    stage_ms = {name: (t1.ms[i] - t0.ms[i]) / tsteps for name, i in
                 (("bc", abi.NS_T_BC), ("fgh", abi.NS_T_FGH), ("rhs", abi.NS_T_RHS),
                  ("sor", abi.NS_T_SOR), ("defect", abi.NS_T_DEFECT), ("project", abi.NS_T_PROJECT),
                  ("other", abi.NS_T_OTHER))}
@@ -73,7 +84,7 @@ def measure(prm, steps, warmup):
         "mcells": n * steps / secs / 1e6,
         "ms_per_step": secs * 1e3 / steps,
         "sor_avg_ms": sor_ms / max(sor_launches, 1),
-        "sor_launches_per_step": sor_launches / steps,
+        "sor_launches_per_step": sor_launches / tsteps,
         "sor_gbs": sor_bytes / (sor_ms * 1e-3) / 1e9 if sor_ms > 0 else 0.0,
         "sor_bytes_per_launch": sor_bytes / max(sor_launches, 1),
         "stage_ms": stage_ms,
@@ -107,7 +118,9 @@ def copy_bandwidth(gib=2.0, reps=5):
 def measure_batched(steps):
     """The batched workload: 64 cavities (sizes U{24..96}, Re U[50, 1000],
     seed 4), adaptive dt (tau 0.5), FP32-mixed, one handle; one launch per
-    sweep covers all of them."""
+    stage (one per pass of sweeps) covers all of them.  Throughput on a
+    handle without stage timers; the sweep figures from one timed step on a
+    second handle."""
     import torch
 
     import nsworkloads as W
@@ -115,23 +128,29 @@ def measure_batched(steps):
     from paper_1201_2118_amd.solver import Solver
 
     prms, _ = W.batched_64()
-    prms = [dict(p, precision="mixed", flags=abi.NS_TIMING if i == 0 else 0) for i, p in enumerate(prms)]
-    s = Solver(prms, device="cuda:0")
+    s = Solver([dict(p, precision="mixed", flags=0) for p in prms], device="cuda:0")
     s.step(1)
-    t0 = s.timing()
     torch.cuda.synchronize()
     a = time.perf_counter()
     s.step(steps)
     torch.cuda.synchronize()
     b = time.perf_counter()
-    t1 = s.timing()
     cells = sum(p["nx"] * p["ny"] * p["nz"] for p in prms)
     sweeps = sum(s.stats(i)["sweeps_total"] for i in range(len(prms)))
     steps_done = sum(s.stats(i)["steps"] for i in range(len(prms)))
+    tile = [s.timing().sor_tile[0], s.timing().sor_tile[1]]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    s = Solver([dict(p, precision="mixed", flags=abi.NS_TIMING if i == 0 else 0, tile=tuple(tile))
+                for i, p in enumerate(prms)], device="cuda:0")
+    s.step(1)
+    t0 = s.timing()
+    s.step(1)
+    t1 = s.timing()
+    s.close()
     sor_ms = t1.ms[abi.NS_T_SOR] - t0.ms[abi.NS_T_SOR]
     sor_bytes = t1.sor_bytes - t0.sor_bytes
-    tile = [t1.sor_tile[0], t1.sor_tile[1]]
-    s.close()
     return {"value": round(cells * steps / (b - a) / 1e6, 2), "unit": "Mcell-steps/s", "instances": len(prms),
             "cells": cells, "steps": steps, "ms_per_step": round((b - a) * 1e3 / steps, 3),
             "mean_sweeps_per_instance_step": round(sweeps / steps_done, 1),
