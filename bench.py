@@ -245,12 +245,19 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="after the runs, copy this many GiB device-to-device once (a plain copy of "
                          "known size that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched workload (--batched-steps steps) and print its figures "
+                         "as one JSON line (for profiling it alone)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: there is no multi-GPU path (the domain would be "
               "split into z slabs with halo exchange). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.batched_only:
+        print(json.dumps(measure_batched(max(args.batched_steps, 1))), flush=True)
+        return
 
     import nsworkloads as W
 
