@@ -186,7 +186,7 @@ __device__ __forceinline__ void fgh_cells(const Geo& g, int zr, const CellBlk& b
   // All three components are formed at every cell (their stencils stay
   // inside the padded arrays) and stored where they are unknowns: the body
   // is one straight block, so the loads of all three are in flight together.
-  for_cells(g, zr, blk, [&](int ci, int cj, int ck, long c) {
+  for_cells<2>(g, zr, blk, [&](int ci, int cj, int ck, long c) {
     double Fv, Gv, Hv;
     {  // F on the x face i
       const double q = u[c], qe = u[c + 1], qw = u[c - 1], qn = u[c + sx], qs = u[c - sx],

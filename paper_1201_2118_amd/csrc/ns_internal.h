@@ -99,12 +99,12 @@ size_t reduce_blocks(const Geo& g);  // partial-sum slots any reduction may need
 // per row.  Kernels without a reduction take short runs (many workgroups);
 // kernels with one take runs long enough that about `target` workgroups
 // remain, whose partial sums the last workgroup adds up (measured at 512^3:
-// 1024 for the rhs and the time step, 2048 for the defect).
+// 1024, i.e. whole z columns there).
 #ifndef NS_CELL_Z
 #define NS_CELL_Z 4  // planes per workgroup, kernels without a reduction
 #endif
 constexpr int kCellX = 64, kCellY = 4;
-constexpr long kRedRhs = 1024, kRedDefect = 2048;
+constexpr long kRedRhs = 1024, kRedDefect = 1024;
 inline int cell_zrun(const Geo& g, long target) {
   const long cols = (long)((g.nx + kCellX - 1) / kCellX) * ((g.ny + kCellY - 1) / kCellY);
   long z = NS_CELL_Z;
@@ -134,8 +134,9 @@ __device__ __forceinline__ CellBlk own_blk() {
                  gridDim.x * gridDim.y * gridDim.z};
 }
 // f(i, j, k, c) for every interior cell of workgroup b's (x, y) tile and
-// run of zr planes.
-template <class F>
+// run of zr planes; UNROLL planes per loop trip (their loads in flight
+// together).
+template <int UNROLL = 1, class F>
 __device__ __forceinline__ void for_cells(const Geo& g, int zr, const CellBlk& b, F&& f) {
   const int i = b.x * kCellX + threadIdx.x + 1;
   const int j = b.y * kCellY + threadIdx.y + 1;
@@ -143,6 +144,7 @@ __device__ __forceinline__ void for_cells(const Geo& g, int zr, const CellBlk& b
   const int k0 = b.z * zr + 1;
   const int k1 = min(g.nz, k0 + zr - 1);
   long c = (long)k0 * g.sxy + (long)j * g.sx + i;
+#pragma unroll(UNROLL)
   for (int k = k0; k <= k1; k++, c += g.sxy) f(i, j, k, c);
 }
 template <class F>
