@@ -139,12 +139,19 @@ typedef struct {
                             fewest equal z chunks of at most k planes */
 } ns_timing;
 
-/* Fill *p with the defaults of the 16^3 lid-driven cavity (Re 100, dt 0.01,
+/* Source: the lid-driven cavity at Re 100 of the paper's "Code Validation
+ * and Verification" section (grid, dt and solver settings are an extension:
+ * the paper prints none).
+ * Fill *p with the defaults of the 16^3 lid-driven cavity (Re 100, dt 0.01,
  * gamma 0.5, omega 1.7, tol 1e-6, 200 sweeps, lid (1,0,0) on +z, FP64).
  * Host only; never fails for a non-NULL pointer. */
 ns_status ns_params_default(ns_params *p);
 
-/* Create a solver for n_instances independent domains (params[n_instances]).
+/* Source: the problem eq. (1) states ("Background and Governing Equations":
+ * nu, body force f, phi = p / rho with rho = 1) on the regular staggered grid
+ * with one ghost layer ("MPI-Based Data Parallelism in Cactus"); several
+ * instances per handle are an extension (many independent cavities).
+ * Create a solver for n_instances independent domains (params[n_instances]).
  * hip_stream: a hipStream_t (NULL = the default stream) that every call of
  * this handle uses.  Validates every parameter (NS_E_INVALID), checks the
  * explicit stability bounds of a fixed dt -- diffusion number
@@ -154,21 +161,29 @@ ns_status ns_params_default(ns_params *p);
 ns_status ns_create(const ns_params *params, int32_t n_instances, void *hip_stream,
                     ns_solver **out);
 
-/* Copy one field of instance inst in (layout above).  Setting u, v or w
+/* Source: the staggered (MAC) placement of velocity and pressure the
+ * paragraph after eq. (1) names; the ghost layer as above.
+ * Copy one field of instance inst in (layout above).  Setting u, v or w
  * starts a new recording epoch for ns_backward. */
 ns_status ns_set_state(ns_solver *s, int32_t inst, int32_t field, const double *src,
                        int32_t on_device);
 
-/* Advance every instance nsteps steps.  stats: NULL or an array of
+/* Source: one time step of the CFD code ("CFD Implementation"; eq. (1));
+ * its last stage is the UPDATE_VELOCITY kernel of the descriptor listing in
+ * "CaCUDA Kernel Abstraction".
+ * Advance every instance nsteps steps.  stats: NULL or an array of
  * n_instances entries that receives the cumulative statistics.  Returns
  * NS_E_NONFINITE if a NaN/Inf appears (stats.steps counts completed steps). */
 ns_status ns_step(ns_solver *s, int32_t nsteps, ns_stats *stats);
 
-/* Copy one field of instance inst out (layout above). */
+/* Source: as ns_set_state.
+ * Copy one field of instance inst out (layout above). */
 ns_status ns_get_state(const ns_solver *s, int32_t inst, int32_t field, double *dst,
                        int32_t on_device);
 
-/* Reverse-mode gradient of a loss of the final velocity with respect to the
+/* Source: an extension beyond the paper (the paper has no adjoint): the
+ * transpose of the step ns_step computes.
+ * Reverse-mode gradient of a loss of the final velocity with respect to the
  * velocity set at the start of the current recording epoch:
  * g_final[3] = dL/d(u,v,w)(T) (padded layout; only unknowns are read),
  * g_init[3]  = out: dL/d(u,v,w)(0) (zero off the unknowns).
@@ -182,9 +197,14 @@ ns_status ns_get_state(const ns_solver *s, int32_t inst, int32_t field, double *
 ns_status ns_backward(ns_solver *s, int32_t inst, const double *const g_final[3],
                       double *const g_init[3], int32_t on_device);
 
-/* Stage timers accumulated while NS_TIMING is set on instance 0. */
+/* Source: an extension for measurement (the paper reports whole-code
+ * GFlop/s in "Performance and Scalability", no per-stage times).
+ * Stage timers accumulated while NS_TIMING is set on instance 0.  Returns
+ * NS_E_INVALID for a NULL handle or out pointer. */
 ns_status ns_get_timing(const ns_solver *s, ns_timing *out);
 
+/* Frees every device buffer and host resource of the handle; NULL is a
+ * no-op.  The handle's stream is the caller's and is not destroyed. */
 void ns_destroy(ns_solver *s);
 
 /* Message of the last failure of this handle (or of the last ns_create

@@ -139,3 +139,55 @@ def test_defect_correction_reaches_dense_solution(oracle_mod):
     got = _pins.interior(p) - _pins.interior(p).mean()
     want = _pins.dense_solve(prm, _pins.interior(rhs))
     assert _pins.rel(got, want) < 1e-9
+
+
+@pytest.mark.parametrize("eta,tol", [(0.1, 1e-9), (0.03, 1e-11)])
+def test_defect_correction_inner_stop_rule(oracle_mod, eta, tol):
+    """Replay of the defect-correction solve with every residual taken from
+    the Kronecker-product matrix: outer residual r = rhs - A p; the inner
+    sweeps on A e = r start from e = 0 and stop at the first sweep with
+    RMS(r - A e) <= eta RMS(r); then p += e; the outer loop stops once
+    RMS(r) <= tol RMS(rhs).  The oracle's sweep and outer counts and its
+    pressure must equal the replay's (an inner rule one sweep early or
+    late, or measured against RMS(rhs), changes the counts)."""
+    prm = _prm(7, 6, 5, bc=(0, 0, 0), lx=1.0, ly=0.8, lz=1.2, tol=tol, itermax=5000)
+    prm["eta"] = eta
+    o = oracle_mod.Oracle(prm)
+    rhs = _zero_mean_rhs(prm, 61)
+    p0 = W.random_field(prm, 62, 0.1)
+    p = p0.copy()
+    n, res, outer = o.sor_defect(p, rhs)
+
+    A = _pins.poisson_matrix(prm)
+    b = _pins.interior(rhs).ravel()
+    rms = lambda x: float(np.sqrt(np.mean(x * x)))
+    thr = tol * rms(b)
+    q = p0.copy()
+    sweeps = outers = 0
+    inner_counts = []
+    while True:
+        r = b - A @ _pins.interior(q).ravel()
+        ro = rms(r)
+        if ro <= thr or sweeps >= prm["itermax"]:
+            break
+        outers += 1
+        rf = np.zeros(o.shape)
+        _pins.interior(rf)[...] = r.reshape(5, 6, 7)
+        e = np.zeros(o.shape)
+        k = 0
+        prev = None
+        while sweeps < prm["itermax"]:
+            o.sor_sweep(e, rf)
+            sweeps += 1
+            k += 1
+            re_ = rms(r - A @ _pins.interior(e).ravel())
+            if re_ <= eta * ro:
+                assert prev is None or prev > eta * ro
+                break
+            prev = re_
+        inner_counts.append(k)
+        _pins.interior(q)[...] += _pins.interior(e)
+    assert outers >= 3 and min(inner_counts) >= 2, inner_counts
+    assert (n, outer) == (sweeps, outers), ((n, outer), (sweeps, outers), inner_counts)
+    assert abs(res - ro) <= 1e-6 * ro
+    assert _pins.rel(_pins.interior(p), _pins.interior(q)) < 1e-12
