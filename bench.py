@@ -13,8 +13,11 @@ the same grid and reported beside it.
 Prints one JSON line.  ``roofline`` covers the dominant kernel (the fused
 red-black sweep): algorithmic bytes per launch over its average duration,
 measured with HIP events on the handle's stream inside the timed region.
-``cpu_baseline`` times the FP64 oracle on a bounded sample of the same
-workload on this host.
+``cpu_baseline`` times the FP64 oracle on two full steps of the same
+workload on this host; the GPU's FP64 and mixed forms run the same two
+steps and their errors against the oracle are reported
+(``errors_vs_oracle``), as is the mixed form's error against the FP64 form
+over the warmup and timed steps (``mixed_vs_fp64``).
 """
 from __future__ import annotations
 
@@ -40,11 +43,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measure(prm, steps, warmup):
+def measure(prm, steps, warmup, keep_state=False):
     """Throughput of K steps on a handle without stage timers (HIP events
     around every launch would add their own gaps to the step), then the
     per-stage and per-launch figures from a second handle of the same grid
-    with NS_TIMING (same sweep shape: the autotuner caches it per grid)."""
+    with NS_TIMING (same sweep shape: the autotuner caches it per grid).
+    keep_state: also return the final u, v, w of the timed handle (FP64
+    device tensors) for the error legs."""
     import torch
 
     from paper_1201_2118_amd import abi
@@ -59,6 +64,7 @@ def measure(prm, steps, warmup):
     torch.cuda.synchronize()
     b = time.perf_counter()
     st = s.stats()
+    final = [s.get(f) for f in "uvw"] if keep_state else None
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -90,6 +96,7 @@ def measure(prm, steps, warmup):
         "stage_ms": stage_ms,
         "stats": st,
         "tile": tile,
+        "final": final,
     }
 
 
@@ -201,33 +208,91 @@ def step_bytes(n, sweeps, mixed, outers=1, per_launch=1):
     return n * (112 + 24 * launches)
 
 
-def cpu_baseline(prm):
-    """The FP64 oracle, untuned, on this host: one step of the same grid
-    with 2 SOR sweeps, plus 2 further sweep+residual passes to price a sweep;
-    scaled to the workload's sweeps per step."""
-    import numpy as np
+def unknowns(prm, comp):
+    """Slices (k, j, i) of the unknowns of velocity component comp (0, 1, 2)
+    or of the cells (3) in the padded layout: faces 1..n-1 along a wall axis
+    normal to the component, 1..n otherwise."""
+    n = [prm["nx"], prm["ny"], prm["nz"]]
+    bc = prm.get("bc", (0, 0, 0))
+    hi = list(n)
+    if comp < 3 and not bc[comp]:
+        hi[comp] -= 1
+    return (slice(1, hi[2] + 1), slice(1, hi[1] + 1), slice(1, hi[0] + 1))
+
+
+def velocity_error(a, b, prm):
+    """max over the components of max |a - b| over that component's unknowns,
+    divided by the velocity scale of b (max |b| over all three); a, b are
+    sequences (u, v, w) of torch tensors or numpy arrays.  Also returns the
+    same per component relative to the component's own max |b|."""
+    scale, diff, own = 0.0, [], []
+    for c in range(3):
+        sl = unknowns(prm, c)
+        x, y = a[c][sl], b[c][sl]
+        d = float(abs(x - y).max())
+        m = float(abs(y).max())
+        scale = max(scale, m)
+        diff.append(d)
+        own.append(d / m if m > 0 else d)
+    return max(diff) / (scale if scale > 0 else 1.0), own
+
+
+def pressure_error(a, b, prm):
+    sl = unknowns(prm, 3)
+    x = a[sl] - a[sl].mean()
+    y = b[sl] - b[sl].mean()
+    return float(abs(x - y).max() / abs(y).max())
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_leg(prm, nsteps=2):
+    """The FP64 oracle, untuned, on this host: ``nsteps`` full steps of the
+    workload from rest (every sweep of every step), timed as the CPU
+    baseline; the GPU's FP64 and mixed forms run the same steps from the
+    same start and are compared with it (velocity relative to the velocity
+    scale, pressure after mean removal)."""
+    import torch
 
     import oracle
+    from paper_1201_2118_amd.solver import Solver
 
-    p = dict(prm, tol=0.0, itermax=2)
-    o = oracle.Oracle(p)
+    o = oracle.Oracle(dict(prm, precision="fp64"))
     a = time.perf_counter()
-    o.run(1)
-    t_step2 = time.perf_counter() - a
-    extra = 40
-    a = time.perf_counter()
-    for _ in range(extra):
-        o.sor_sweep(o.p, o.rhs)
-        o.residual(o.p, o.rhs)
-    t_sweep = (time.perf_counter() - a) / extra
-    sweeps = prm["itermax"]
-    t_full = t_step2 + (sweeps - 2) * t_sweep
+    rc = o.run(nsteps)
+    secs = time.perf_counter() - a
+    if rc != 0:
+        raise RuntimeError(f"oracle run failed ({rc})")
+    ref = [o.field(f) for f in "uvw"]
     n = prm["nx"] * prm["ny"] * prm["nz"]
+    errs = {"steps": nsteps, "oracle_sweeps": int(o.stats.sweeps_total)}
+    for form in ("fp64", "mixed"):
+        s = Solver(dict(prm, precision=form, flags=0), device="cuda:0")
+        s.step(nsteps)
+        got = [s.get_np(f) for f in "uvw"]
+        vel, own = velocity_error(got, ref, prm)
+        errs[form] = {"vel_rel": vel, "vel_rel_own_max": own,
+                      "p_rel": pressure_error(s.get_np("p"), o.p, prm),
+                      "sweeps": int(s.stats()["sweeps_total"])}
+        s.close()
+        del s, got
+        torch.cuda.empty_cache()
+    base = {"value": n * nsteps / secs / 1e6, "unit": "Mcell-steps/s", "cores": oracle.threads(),
+            "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"{nsteps} full steps of the {prm['nx']}^3 workload from rest "
+                      f"({int(o.stats.sweeps_total)} sweeps, {secs:.1f} s), FP64; the run the "
+                      f"errors_vs_oracle figures compare against"}
     del o
-    return {"value": n / t_full / 1e6, "unit": "Mcell-steps/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"one {prm['nx']}^3 step with 2 sweeps ({t_step2:.1f} s) plus {extra} sweep+residual "
-                      f"passes ({t_sweep:.3f} s each), scaled to {sweeps} sweeps per step; FP64"}
+    return base, errs
 
 
 def main():
@@ -273,7 +338,7 @@ def main():
             # FP64 two-sweep tiles have 16 rows
             rows = args.tile[0] if form == "mixed" or args.tile[0] <= 16 else 16
             cfg["tile"] = (rows, args.tile[1])
-        r = measure(cfg, args.steps, args.warmup)
+        r = measure(cfg, args.steps, args.warmup, keep_state=args.only == "both")
         st = r["stats"]
         sweeps = st["sweeps_total"] / max(st["steps"], 1)
         k = 2 if r["tile"][0] >= 16 else 1
@@ -289,13 +354,22 @@ def main():
     per_launch = 2 if dom["tile"][0] >= 16 else 1
     tag = ("sor_pass" if per_launch == 2 else "sor_fused") + ("_f32" if f32 else "_f64")
     traffic = traffic_from_profile(tag, dom["tile"]) if args.n == 512 else None
-    roof = {"bound": "hbm", "achieved": round(dom["sor_gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(dom["sor_gbs"] / PEAK_HBM_GBS, 4),
+    # Algorithmic bytes per launch: 12 (FP32) / 24 (FP64) bytes per cell per
+    # sweep times the sweeps one launch does (a two-sweep pass is priced as
+    # two sweeps); the bytes of a single pass over the data and the counter
+    # traffic are kept beside it.
+    one_pass = dom["sor_gbs"]
+    achieved = per_launch * one_pass
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": round(traffic) if traffic else None,
             "kernel": "red-black SOR, %d sweep(s) per launch (%s)" % (per_launch, "FP32" if f32 else "FP64"),
             "sweeps_per_launch": per_launch,
-            "bytes_per_launch": dom["sor_bytes_per_launch"], "avg_launch_ms": round(dom["sor_avg_ms"], 5),
-            "sweep_equivalent_gbs": round(per_launch * dom["sor_gbs"], 1),
+            "bytes_per_launch": per_launch * dom["sor_bytes_per_launch"],
+            "avg_launch_ms": round(dom["sor_avg_ms"], 5),
+            "one_pass_gbs": round(one_pass, 1),
+            "one_pass_frac": round(one_pass / PEAK_HBM_GBS, 4),
+            "traffic_gbs": round(traffic / (dom["sor_avg_ms"] * 1e-3) / 1e9, 1) if traffic else None,
             "limiter": ("instruction issue and waits: VALU 64% busy, 45% of the wave cycles waiting on "
                         "memory / LDS / the per-plane barrier (SQ counters)") if per_launch == 2 and f32
                        else ("vector-ALU issue (two sweeps per launch)" if per_launch == 2 else "HBM"),
@@ -330,6 +404,17 @@ def main():
                        "gbs_one_sweep_model": round(f["one_sweep_gbs"], 1), "sor_gbs": round(f["sor_gbs"], 1),
                        "sor_avg_ms": round(f["sor_avg_ms"], 5), "tile": f["tile"],
                        "stage_ms": {k: round(v, 4) for k, v in f["stage_ms"].items()}}
+    if "fp64" in res and "mixed" in res:
+        vel, own = velocity_error(res["mixed"]["final"], res["fp64"]["final"], prm)
+        out["mixed_vs_fp64"] = {"steps": args.warmup + args.steps, "vel_rel": vel, "vel_rel_own_max": own,
+                                "note": "both forms from rest over the warmup and timed steps; velocity "
+                                        "error relative to the FP64 run's velocity scale (and per component "
+                                        "relative to its own max)"}
+        log(f"mixed vs fp64 after {args.warmup + args.steps} steps: {vel:.2e}")
+    for r in res.values():
+        r["final"] = None
+    import torch
+    torch.cuda.empty_cache()
     if args.batched_steps > 0:
         out["batched"] = measure_batched(args.batched_steps)
         log(f"batched: {out['batched']['value']} Mcell-steps/s over {out['batched']['instances']} cavities")
@@ -345,8 +430,9 @@ def main():
         out["copy_probe_bytes"] = nbytes
         del a, c
     if not args.no_cpu:
-        log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(prm)
+        log("oracle leg: cpu baseline and GPU errors against the oracle")
+        out["cpu_baseline"], out["errors_vs_oracle"] = oracle_leg(prm)
+        log(f"errors vs oracle: {out['errors_vs_oracle']}")
     print(json.dumps(out), flush=True)
 
 

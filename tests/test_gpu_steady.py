@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import nsworkloads as W
+from tests import gpu_util as U
 
 pytestmark = pytest.mark.gpu
 
@@ -57,3 +58,28 @@ def test_steady_cavity_re100_self_convergence():
     # the primary vortex: reversed flow below the lid on the vertical centreline
     uc = runs[64][0]
     assert uc.min() < 0 and uc[-1] > 0.5
+
+
+@pytest.mark.timeout(600)
+def test_steady_cavity_re100_matches_oracle():
+    n, dt, t_end = 16, 0.01, 20.0
+    prm = W.cavity(n, re=100.0, dt=dt, tol=1e-8, itermax=500)
+    nsteps = int(round(t_end / dt))
+    s = U.gpu_run(prm, nsteps)
+    o, rc = U.oracle_run(prm, nsteps)
+    assert rc == 0
+    st = s.stats()
+    print(f"{n}^3 steady cavity: GPU {st['sweeps_total']} sweeps, oracle {o.stats.sweeps_total}", flush=True)
+    assert st["steps"] == nsteps and abs(st["t"] - o.stats.t) < 1e-12
+    assert st["sweeps_total"] == o.stats.sweeps_total
+    errs = U.compare_state(s, o, prm, 1e-12)
+    h = n // 2
+    u, w = s.get_np("u"), s.get_np("w")
+    uo, wo = o.field("u"), o.field("w")
+    uc = 0.5 * (u[1:n + 1, h, h] + u[1:n + 1, h + 1, h])
+    uco = 0.5 * (uo[1:n + 1, h, h] + uo[1:n + 1, h + 1, h])
+    wc = 0.5 * (w[h, h, 1:n + 1] + w[h, h + 1, 1:n + 1])
+    wco = 0.5 * (wo[h, h, 1:n + 1] + wo[h, h + 1, 1:n + 1])
+    assert np.abs(uc - uco).max() <= 1e-12 * np.abs(uco).max()
+    assert np.abs(wc - wco).max() <= 1e-12 * np.abs(wco).max()
+    print(f"{n}^3 steady cavity vs oracle: {errs}", flush=True)
