@@ -203,6 +203,32 @@ ns_status ns_backward(ns_solver *s, int32_t inst, const double *const g_final[3]
  * NS_E_INVALID for a NULL handle or out pointer. */
 ns_status ns_get_timing(const ns_solver *s, ns_timing *out);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the step of ns_step for one FP64 domain
+ * without a handle and without any allocation.
+ * params: one instance, precision NS_FP64, checkpoint_every 0, no NS_TIMING
+ * (else NS_E_INVALID); validated and stability-checked as in ns_create.
+ * u, v, w, p: device memory of the current device, FP64, the padded layout
+ * above, read and overwritten in place with the state after nsteps steps
+ * (the result equals ns_create + ns_set_state of u, v, w, p + ns_step +
+ * ns_get_state).  hip_stream: the stream every launch goes to (NULL = the
+ * default stream); the call returns after the steps are done.  stats: NULL
+ * or one ns_stats that receives this call's statistics.
+ * Scratch: F, G, H, rhs, a second pressure buffer, partial sums and the
+ * control block live in one static device array of 21.5 MB per device (held
+ * until the process ends), so (nx+2)(ny+2)(nz+2) must not exceed 524288
+ * (e.g. 78^3 interior cells); larger grids return NS_E_INVALID.  The array
+ * keeps the last call's contents and is cleared at the start of each call.
+ * Calls on one device share it: the library serialises its own calls per
+ * device with a lock, and any other use of the array that overlapped a call
+ * would race.  Errors: NS_E_INVALID (arguments, sizes, pointers that are not
+ * memory of the current device), NS_E_NONFINITE, NS_E_DEVICE; the message is
+ * ns_last_error(NULL).  No hipMalloc, hipFree, pinned-host or other device
+ * allocation happens in the call (the first call on a device looks up the
+ * array's address and builds the host-side solver shell once). */
+ns_status ns_step_noalloc(const ns_params *params, double *u, double *v, double *w, double *p,
+                          int32_t nsteps, void *hip_stream, ns_stats *stats);
+
 /* Frees every device buffer and host resource of the handle; NULL is a
  * no-op.  The handle's stream is the caller's and is not destroyed. */
 void ns_destroy(ns_solver *s);

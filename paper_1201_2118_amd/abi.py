@@ -22,7 +22,7 @@ NS_FP64, NS_MIXED = 0, 1
 NS_ALLOW_UNSTABLE, NS_TIMING = 1, 2
 NS_T_BC, NS_T_FGH, NS_T_RHS, NS_T_SOR, NS_T_DEFECT, NS_T_PROJECT, NS_T_OTHER, NS_T_COUNT = 0, 1, 2, 3, 4, 5, 6, 8
 EXPORTED = ("ns_params_default", "ns_create", "ns_set_state", "ns_step", "ns_get_state",
-            "ns_backward", "ns_get_timing", "ns_destroy", "ns_last_error")
+            "ns_backward", "ns_get_timing", "ns_destroy", "ns_last_error", "ns_step_noalloc")
 
 
 class ns_params(ctypes.Structure):
@@ -91,6 +91,7 @@ def load(path: str = LIB_PATH):
         "ns_get_timing": (ctypes.c_int, [vp, P(ns_timing)]),
         "ns_destroy": (None, [vp]),
         "ns_last_error": (ctypes.c_char_p, [vp]),
+        "ns_step_noalloc": (ctypes.c_int, [P(ns_params), vp, vp, vp, vp, ctypes.c_int32, vp, P(ns_stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -141,6 +142,12 @@ def ns_get_timing(handle, out: ns_timing) -> int:
 
 def ns_destroy(handle) -> None:
     load().ns_destroy(handle)
+
+
+def ns_step_noalloc(params: ns_params, u_ptr: int, v_ptr: int, w_ptr: int, p_ptr: int, nsteps: int,
+                    hip_stream: int | None, stats) -> int:
+    return load().ns_step_noalloc(ctypes.byref(params), u_ptr, v_ptr, w_ptr, p_ptr, nsteps, hip_stream,
+                                  None if stats is None else ctypes.byref(stats))
 
 
 def ns_last_error(handle=None) -> str:

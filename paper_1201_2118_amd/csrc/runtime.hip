@@ -66,6 +66,11 @@ struct Inst {
   std::vector<double*> hist;
 };
 
+// Launches of one solve, to find the buffer of the accepted iterate.
+struct SweepLaunch {
+  int m1, ns, in, out;  // first sweep index, sweeps, input / output buffer
+};
+
 struct EvRec {
   hipEvent_t a, b;
   int stage;
@@ -105,6 +110,9 @@ struct ns_solver {
   hipStream_t aux[kAux] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kAux] = {};
+  // launches of the current FP64 solve (kept across solves so that its
+  // capacity is reused)
+  std::vector<SweepLaunch> launch_log;
 };
 
 namespace {
@@ -549,10 +557,6 @@ hipError_t sweep_launch(ns_solver* s, Inst& I, const T* p_in, T* p_out, const T*
                              zero_in, inner, I.shape);
 }
 
-// Launches of one solve, to find the buffer of the accepted iterate.
-struct SweepLaunch {
-  int m1, ns, in, out;  // first sweep index, sweeps, input / output buffer
-};
 
 // Buffer holding iterate f, or -1.  An iterate that a two-sweep pass held
 // only in registers is swept again (forced, bitwise the same arithmetic)
@@ -586,7 +590,8 @@ ns_status solve_fp64(ns_solver* s, int idx, double* P[2], int* cur, int* sweeps)
   const bool pairs = shape_is_pass(I.shape);
   int m = 0;     // newest iterate launched
   int b = *cur;  // its buffer
-  std::vector<SweepLaunch> L;
+  std::vector<SweepLaunch>& L = s->launch_log;
+  L.clear();
   int pred = std::min(std::max(I.pred + 2, 4), itermax + 1);
   bool first = true;
   for (;;) {
@@ -1273,6 +1278,76 @@ ns_status save_state(ns_solver* s, Inst& I, const State& from, State& to) {
   return NS_OK;
 }
 
+// ---- allocation-free step -------------------------------------------------------
+// ns_step_noalloc keeps everything beyond the caller's fields in one static
+// device array: the predictor fields F, G, H, the right-hand side and the
+// second pressure buffer (kNaEntries FP64 entries each, padded layout), the
+// partial sums of the reductions and one control block.  Each device the
+// library runs on holds its own copy until the process ends.
+constexpr long kNaEntries = 1L << 19;  // padded entries (nx+2)(ny+2)(nz+2) per field
+constexpr long kNaPartials = 1L << 16;
+constexpr long kNaCtl = (long)(sizeof(Ctl) / sizeof(double));
+constexpr long kNaDoubles = 5 * kNaEntries + kNaPartials + kNaCtl;
+static_assert(sizeof(Ctl) % sizeof(double) == 0, "control block is a whole number of doubles");
+static __device__ __align__(256) double scratch[kNaDoubles];
+
+// Host side, per device: the device address of `scratch` (from
+// hipGetSymbolAddress; the array's name is only a host stand-in), a solver
+// shell whose single instance is pointed at the caller's fields and the
+// scratch on every call, and the lock that keeps calls on one device from
+// overlapping.
+struct NaDevice {
+  bool ready = false;
+  double* ptr = nullptr;
+  ns_solver* shell = nullptr;
+  Ctl hctl{};
+  std::mutex mu;
+};
+constexpr int kNaMaxDevices = 64;
+NaDevice g_na[kNaMaxDevices];
+std::mutex g_na_setup_mu;
+
+// Clears the scratch fields and partial sums (the state a freshly created
+// handle starts from) and writes the control block's initial dt.
+__global__ void k_na_init(double* __restrict__ q, long n, Ctl* __restrict__ ctl, double dt) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) q[i] = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctl c{};
+    c.dt = dt;
+    *ctl = c;
+  }
+}
+
+ns_status na_setup(int dev, NaDevice** out) {
+  std::lock_guard<std::mutex> lk(g_na_setup_mu);
+  NaDevice& D = g_na[dev];
+  if (!D.ready) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, NS_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    D.ptr = (double*)ptr;
+    D.shell = new ns_solver();
+    D.shell->in.resize(1);
+    D.shell->launch_log.reserve(4096);
+    D.shell->hctl = &D.hctl;
+    D.shell->device = dev;
+    D.ready = true;
+  }
+  *out = &D;
+  return NS_OK;
+}
+
+// NS_OK when q points into device memory of device dev.
+ns_status is_device_memory(const void* q, int dev) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, q) != hipSuccess) {
+    (void)hipGetLastError();
+    return NS_E_INVALID;
+  }
+  return a.type == hipMemoryTypeDevice && a.device == dev ? NS_OK : NS_E_INVALID;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1650,6 +1725,76 @@ void ns_destroy(ns_solver* s) {
   (void)hipFree(s->ctl_all);
   (void)hipFree(s->stage);
   delete s;
+}
+
+ns_status ns_step_noalloc(const ns_params* params, double* u, double* v, double* w, double* p, int32_t nsteps,
+                          void* hip_stream, ns_stats* stats) {
+  if (!params) return fail(nullptr, NS_E_INVALID, "params is NULL");
+  ns_status st = validate(*params, 0);
+  if (st != NS_OK) return st;
+  if (params->precision != NS_FP64) return fail(nullptr, NS_E_INVALID, "ns_step_noalloc: NS_FP64 only");
+  if (params->checkpoint_every != 0) return fail(nullptr, NS_E_INVALID, "ns_step_noalloc: no recording");
+  if (params->flags & NS_TIMING) return fail(nullptr, NS_E_INVALID, "ns_step_noalloc: no stage timers");
+  if (nsteps < 0) return fail(nullptr, NS_E_INVALID, "nsteps must be >= 0");
+  if (!u || !v || !w || !p) return fail(nullptr, NS_E_INVALID, "u, v, w and p must be device pointers");
+  const Geo g = make_geo(*params);
+  if (g.ntot > kNaEntries)
+    return fail(nullptr, NS_E_INVALID,
+                "ns_step_noalloc: (nx+2)(ny+2)(nz+2) exceeds the static scratch (524288 entries per field)");
+  if ((long)reduce_blocks(g) > kNaPartials)
+    return fail(nullptr, NS_E_INVALID, "ns_step_noalloc: too many partial sums for the static scratch");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(nullptr, NS_E_DEVICE, "no HIP device");
+  if (dev >= kNaMaxDevices) return fail(nullptr, NS_E_INVALID, "device index beyond the supported range");
+  double* const fields[4] = {u, v, w, p};
+  for (double* q : fields)
+    if (is_device_memory(q, dev) != NS_OK)
+      return fail(nullptr, NS_E_INVALID, "ns_step_noalloc: u, v, w and p must be memory of the current device");
+  NaDevice* D = nullptr;
+  st = na_setup(dev, &D);
+  if (st != NS_OK) return st;
+  std::lock_guard<std::mutex> lk(D->mu);
+  ns_solver* s = D->shell;
+  s->stream = (hipStream_t)hip_stream;
+  Inst& I = s->in[0];
+  I = Inst{};
+  I.prm = *params;
+  I.g = g;
+  I.mixed = false;
+  I.esz = 8;
+  I.bytes = I.pbytes = (size_t)g.ntot * 8;
+  double* base = D->ptr;
+  I.F = base;
+  I.G = base + kNaEntries;
+  I.H = base + 2 * kNaEntries;
+  I.rhs = base + 3 * kNaEntries;
+  I.part = base + 5 * kNaEntries;
+  I.ctl = (Ctl*)(base + 5 * kNaEntries + kNaPartials);
+  I.s.u = u;
+  I.s.v = v;
+  I.s.w = w;
+  I.s.p[0] = p;
+  I.s.p[1] = base + 4 * kNaEntries;
+  I.s.pcur = 0;
+  I.shape = pick_shape(I.prm, g, 8);
+  auto done = [&](ns_status code) {
+    if (code != NS_OK) g_create_err = s->err;
+    if (stats) *stats = I.st;
+    return code;
+  };
+  k_na_init<<<conv_grid(5 * kNaEntries + kNaPartials), 256, 0, s->stream>>>(
+      base, 5 * kNaEntries + kNaPartials, I.ctl, I.prm.dt > 0 ? I.prm.dt : 0.0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return done(fail_hip(s, "scratch clear", e));
+  ns_status ret = NS_OK;
+  for (int n = 0; n < nsteps && ret == NS_OK; n++) ret = step_inst<double>(s, 0, I.s, true);
+  if (ret == NS_OK && I.s.pcur == 1) {
+    e = hipMemcpyAsync(p, I.s.p[1], I.pbytes, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) ret = fail_hip(s, "pressure copy", e);
+  }
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess && ret == NS_OK) ret = fail_hip(s, "stream synchronisation", e);
+  return done(ret);
 }
 
 const char* ns_last_error(const ns_solver* s) {

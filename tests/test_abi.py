@@ -119,3 +119,18 @@ def test_null_arguments():
     assert lib.ns_set_state(None, 0, 0, None, 0) == abi.NS_E_INVALID
     assert lib.ns_get_state(None, 0, 0, None, 0) == abi.NS_E_INVALID
     lib.ns_destroy(None)
+
+
+def test_noalloc_step_validates_before_any_device_call():
+    """ns_step_noalloc rejects bad arguments and grids beyond its static
+    scratch on the host, before it touches a device."""
+    prm = W.cavity(80, ny=80, nz=80, dt=5e-4)  # 82^3 padded entries > 524288
+    code = abi.ns_step_noalloc(make_params(prm), 1, 1, 1, 1, 1, None, None)
+    assert code == abi.NS_E_INVALID and "static scratch" in abi.ns_last_error(None)
+    for edit in (dict(precision="mixed"), dict(checkpoint_every=2), dict(flags=abi.NS_TIMING)):
+        code = abi.ns_step_noalloc(make_params(dict(W.cavity(8), **edit)), 1, 1, 1, 1, 1, None, None)
+        assert code == abi.NS_E_INVALID, edit
+    code = abi.ns_step_noalloc(make_params(W.cavity(8)), 0, 1, 1, 1, 1, None, None)
+    assert code == abi.NS_E_INVALID
+    code = abi.ns_step_noalloc(make_params(W.cavity(8)), 1, 1, 1, 1, -1, None, None)
+    assert code == abi.NS_E_INVALID
