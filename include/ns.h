@@ -76,7 +76,9 @@ enum { NS_BC_WALL = 0, NS_BC_PERIODIC = 1 };
 enum { NS_FP64 = 0, NS_MIXED = 1 };
 enum {
   NS_ALLOW_UNSTABLE = 1, /* accept a fixed dt beyond the stability bounds */
-  NS_TIMING = 2          /* record per-stage GPU times (ns_get_timing) */
+  NS_TIMING = 2,         /* record per-stage GPU times (ns_get_timing) */
+  NS_BATCH_LAUNCHES = 4  /* several instances (flag of instance 0): one launch per stage and per
+                            pass of sweeps, polled by the host, instead of the persistent launch */
 };
 
 typedef struct {

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libns.so")
 
-SOURCES = ["kernels.hip", "sor.hip", "sor_fused.hip", "sor_pass.hip", "adjoint.hip", "runtime.hip"]
+SOURCES = ["kernels.hip", "sor.hip", "sor_fused.hip", "sor_pass.hip", "persist.hip", "adjoint.hip",
+           "runtime.hip"]
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -139,7 +139,7 @@ __device__ __forceinline__ CellBlk own_blk() {
 template <int UNROLL = 1, class F>
 __device__ __forceinline__ void for_cells(const Geo& g, int zr, const CellBlk& b, F&& f) {
   const int i = b.x * kCellX + threadIdx.x + 1;
-  const int j = b.y * kCellY + threadIdx.y + 1;
+  const int j = b.y * (int)blockDim.y + threadIdx.y + 1;
   if (i > g.nx || j > g.ny) return;
   const int k0 = b.z * zr + 1;
   const int k1 = min(g.nz, k0 + zr - 1);
@@ -259,6 +259,61 @@ inline bool stage_reduces(int kind) { return kind == kStageRhs || kind == kStage
 template <class T> hipError_t launch_stage_batched(hipStream_t st, int kind, const StageItem* d_items, int nitems,
                                                   int nblocks);
 hipError_t launch_defect_batched(hipStream_t st, const StageItem* d_items, int nitems, int nblocks);
+
+// ---- persistent batched launch (persist.hip) ----
+// Workgroups of 64 x kPersistWaves threads; cell-stage blocks of 64 x
+// kPersistWaves cells and kPersistZr planes; two-sweep pass tiles of 16
+// rows.
+constexpr int kPersistWaves = 8;
+constexpr int kPersistZr = 4;
+// Statistics of one domain, kept on the device across the launch (the
+// host's ns_stats plus the pressure buffer in use and the sweep time).
+struct PStats {
+  double t, dt_last, res_last;
+  long long sweeps_total;
+  int steps, sweeps_max, steps_unconverged, outer_max;
+  int pcur;          // pressure buffer holding the state
+  int nonfinite;     // a NaN / Inf reached a residual norm
+  double sweep_ticks;  // wall-clock ticks the team's lead spent in Poisson solves
+};
+// One domain of a persistent launch.  Buffers hold the storage type T of
+// the launch (float: mixed precision, double: FP64) except p (FP64).
+struct PItem {
+  Geo g;
+  void* u;
+  void* v;
+  void* w;
+  void* F;
+  void* G;
+  void* H;
+  void* rhs;
+  const void* frc[3];  // body-force fields or null
+  double* p[2];        // pressure buffers
+  void* e[2];          // mixed: correction iterates (FP32)
+  void* r;             // mixed: defect (FP32)
+  double* part;        // partial sums, at least 6 * team + 8 slots
+  Ctl* ctl;            // control block (initial dt in, final state out)
+  PStats* st;
+  unsigned* bar;       // team barrier counter, zero at launch
+  double wall[6][3];
+  double wmax[3];      // largest wall speed per component
+  double gforce[3];
+  double re, tau, gamma, omega, tol, eta;
+  int adaptive;        // dt from the velocity every step
+  int itermax;
+  int team;            // workgroups of the domain's team
+  int cgx, cgy, cgz;   // cell-stage blocks per axis
+};
+// Workgroup b of the launch: its domain (-1: idle) and rank in the team.
+struct PSlot {
+  int item, rank;
+};
+int persistent_resident(bool f32);  // co-resident workgroups of the launch
+// Cooperative launch of nblocks workgroups running nsteps steps of every
+// domain; err: device flag raised when a barrier wait exceeds `limit`
+// wall-clock ticks (the grid then drains).
+hipError_t launch_persistent(hipStream_t st, bool f32, const PItem* items, const PSlot* slots, int nblocks,
+                             int nsteps, int* err, long long limit);
 
 // Adjoint of the predictor in gather form (FP64 only): z = B^T J_Phi(u)^T mu.
 hipError_t launch_adj_fgh(hipStream_t st, const Geo& g, const double* u, const double* v,

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -113,6 +114,20 @@ struct ns_solver {
   // launches of the current FP64 solve (kept across solves so that its
   // capacity is reused)
   std::vector<SweepLaunch> launch_log;
+  // batched: every step of every domain in one persistent launch (teams of
+  // workgroups per domain, device-side barriers and stop rules)
+  bool persist = false;
+  int persist_blocks = 0;
+  long long persist_limit = 0;  // wall-clock ticks a barrier wait may take
+  double clock_khz = 0.0;       // device wall-clock rate
+  PItem* pitems_h = nullptr;    // pinned
+  PItem* pitems_d = nullptr;
+  PSlot* pslots_d = nullptr;
+  PStats* pstats_h = nullptr;   // pinned
+  PStats* pstats_d = nullptr;
+  unsigned* pbar_d = nullptr;
+  int* perr_d = nullptr;
+  int* perr_h = nullptr;        // pinned
 };
 
 namespace {
@@ -207,7 +222,7 @@ ns_status validate(const ns_params& p, int idx) {
       if (!std::isfinite(p.wall_vel[f][c])) return bad("wall velocities must be finite");
   for (int c = 0; c < 3; c++)
     if (!std::isfinite(p.g[c])) return bad("body force must be finite");
-  if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING)) return bad("unknown flag bits");
+  if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING | NS_BATCH_LAUNCHES)) return bad("unknown flag bits");
   if (!(p.tile[0] == -1 || p.tile[0] == 0 || p.tile[0] == 4 || p.tile[0] == 8 || p.tile[0] == 12 ||
         p.tile[0] == 16 || p.tile[0] == 24 || p.tile[0] == 32))
     return bad("tile[0] must be -1, 0, 4, 8, 12, 16, 24 or 32");
@@ -1236,6 +1251,230 @@ ns_status step_batched(ns_solver* s) {
   return ret;
 }
 
+// ---- persistent batched launch ---------------------------------------------------
+// Teams: the co-resident workgroups of the launch are split among the
+// domains.  Workgroup b runs on XCD b mod 8; the domains are dealt to the
+// XCDs longest-processing-time first (by cell count), and the workgroups of
+// an XCD are shared among its domains in proportion to their cell counts
+// (at least one each), so a domain's team sits on one XCD (one L2).
+// Returns false when some XCD would get more domains than workgroups.
+bool persist_teams(const std::vector<long long>& cells, int G, std::vector<PSlot>& slots, std::vector<int>& team) {
+  const int n = (int)cells.size();
+  slots.assign(G, PSlot{-1, 0});
+  team.assign(n, 0);
+  int gx[8];
+  for (int x = 0; x < 8; x++) gx[x] = G / 8 + (x < G % 8 ? 1 : 0);
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; i++) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cells[a] > cells[b]; });
+  long long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<int> on[8];
+  for (int d : ord) {
+    int best = -1;
+    for (int x = 0; x < 8; x++)
+      if ((int)on[x].size() < gx[x] && (best < 0 || load[x] < load[best])) best = x;
+    if (best < 0) return false;
+    on[best].push_back(d);
+    load[best] += cells[d];
+  }
+  for (int x = 0; x < 8; x++) {
+    if (on[x].empty()) continue;
+    long long cx = 0;
+    for (int d : on[x]) cx += cells[d];
+    int sum = 0;
+    for (int d : on[x]) {
+      team[d] = std::max(1, (int)((double)gx[x] * (double)cells[d] / (double)cx));
+      sum += team[d];
+    }
+    // hand out the rest to the domains with the most cells per workgroup,
+    // take back from those with the fewest
+    while (sum < gx[x]) {
+      int best = on[x][0];
+      for (int d : on[x])
+        if ((double)cells[d] / team[d] > (double)cells[best] / team[best]) best = d;
+      team[best]++;
+      sum++;
+    }
+    while (sum > gx[x]) {
+      int best = -1;
+      for (int d : on[x])
+        if (team[d] > 1 && (best < 0 || (double)cells[d] / (team[d] - 1) < (double)cells[best] / (team[best] - 1)))
+          best = d;
+      if (best < 0) return false;
+      team[best]--;
+      sum--;
+    }
+    int slot = 0;
+    for (int d : on[x])
+      for (int r = 0; r < team[d]; r++, slot++) slots[x + 8 * slot] = PSlot{d, r};
+  }
+  return true;
+}
+
+// Sets up the persistent launch of a batched handle; leaves s->persist
+// false (and allocates nothing) when the handle does not qualify.
+ns_status persist_setup(ns_solver* s) {
+  const int n = (int)s->in.size();
+  const bool f32 = s->in[0].mixed;
+  if (s->in[0].prm.flags & NS_BATCH_LAUNCHES) return NS_OK;
+  for (auto& I : s->in)
+    if (I.prm.tile[0] != 0 || I.prm.checkpoint_every > 0 || !pass_grid_ok(I.g, I.esz)) return NS_OK;
+  int coop = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device) != hipSuccess || !coop)
+    return NS_OK;
+  const int G = persistent_resident(f32);
+  if (G < n) return NS_OK;
+  std::vector<long long> cells(n);
+  for (int i = 0; i < n; i++) cells[i] = (long long)s->in[i].g.nx * s->in[i].g.ny * s->in[i].g.nz;
+  std::vector<PSlot> slots;
+  std::vector<int> team;
+  if (!persist_teams(cells, G, slots, team)) return NS_OK;
+  int rate = 0;
+  HCK(s, hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, s->device));
+  s->clock_khz = rate > 0 ? (double)rate : 100000.0;
+  // a barrier wait longer than this gives up (a test lowers it to force
+  // the give-up path); default 30 s
+  double limit_us = 30e6;
+  if (const char* e = getenv("NS_TEAM_WAIT_LIMIT_US")) limit_us = atof(e);
+  s->persist_limit = (long long)(limit_us * s->clock_khz / 1000.0);
+  // partial sums: two halves of 3 per team workgroup (the time step's three
+  // maxima)
+  for (int i = 0; i < n; i++) {
+    Inst& I = s->in[i];
+    const size_t need = 6 * (size_t)team[i] + 8;
+    if (need > reduce_blocks(I.g)) {
+      (void)hipFree(I.part);
+      I.part = nullptr;
+      HCK(s, dmalloc((void**)&I.part, need * sizeof(double)));
+    }
+  }
+  HCK(s, hipHostMalloc((void**)&s->pitems_h, sizeof(PItem) * n, hipHostMallocDefault));
+  HCK(s, hipHostMalloc((void**)&s->pstats_h, sizeof(PStats) * n, hipHostMallocDefault));
+  HCK(s, hipHostMalloc((void**)&s->perr_h, sizeof(int), hipHostMallocDefault));
+  HCK(s, dmalloc((void**)&s->pitems_d, sizeof(PItem) * n));
+  HCK(s, dmalloc((void**)&s->pstats_d, sizeof(PStats) * n));
+  HCK(s, dmalloc((void**)&s->pslots_d, sizeof(PSlot) * G));
+  HCK(s, dmalloc((void**)&s->pbar_d, sizeof(unsigned) * n));
+  HCK(s, dmalloc((void**)&s->perr_d, sizeof(int)));
+  HCK(s, hipMemcpy(s->pslots_d, slots.data(), sizeof(PSlot) * G, hipMemcpyHostToDevice));
+  for (int i = 0; i < n; i++) {
+    PItem& it = s->pitems_h[i];
+    it = PItem{};
+    it.team = team[i];
+  }
+  s->persist_blocks = G;
+  s->persist = true;
+  return NS_OK;
+}
+
+// nsteps steps of every domain in one launch.
+ns_status persist_run(ns_solver* s, int nsteps) {
+  const int n = (int)s->in.size();
+  const bool f32 = s->in[0].mixed;
+  std::vector<long long> sweeps0(n);
+  for (int i = 0; i < n; i++) {
+    Inst& I = s->in[i];
+    PItem& it = s->pitems_h[i];
+    const int team = it.team;
+    it = PItem{};
+    it.team = team;
+    it.g = I.g;
+    it.u = I.s.u;
+    it.v = I.s.v;
+    it.w = I.s.w;
+    it.F = I.F;
+    it.G = I.G;
+    it.H = I.H;
+    it.rhs = I.rhs;
+    for (int c = 0; c < 3; c++) it.frc[c] = I.frc[c];
+    it.p[0] = I.s.p[0];
+    it.p[1] = I.s.p[1];
+    it.e[0] = I.e[0];
+    it.e[1] = I.e[1];
+    it.r = I.r;
+    it.part = I.part;
+    it.ctl = I.ctl;
+    it.st = s->pstats_d + i;
+    it.bar = s->pbar_d + i;
+    for (int f = 0; f < 6; f++)
+      for (int c = 0; c < 3; c++) it.wall[f][c] = I.prm.wall_vel[f][c];
+    wall_speed_max(I.prm, it.wmax);
+    for (int c = 0; c < 3; c++) it.gforce[c] = I.prm.g[c];
+    it.re = I.prm.re;
+    it.tau = I.prm.tau;
+    it.gamma = I.prm.gamma;
+    it.omega = I.prm.omega;
+    it.tol = I.prm.tol;
+    it.eta = I.prm.eta;
+    it.adaptive = I.prm.dt <= 0;
+    it.itermax = I.prm.itermax;
+    it.cgx = (I.g.nx + kCellX - 1) / kCellX;
+    it.cgy = (I.g.ny + kPersistWaves - 1) / kPersistWaves;
+    it.cgz = (I.g.nz + kPersistZr - 1) / kPersistZr;
+    PStats& ps = s->pstats_h[i];
+    ps = PStats{};
+    ps.t = I.st.t;
+    ps.dt_last = I.st.dt_last;
+    ps.res_last = I.st.res_last;
+    ps.sweeps_total = I.st.sweeps_total;
+    ps.steps = I.st.steps;
+    ps.sweeps_max = I.st.sweeps_max;
+    ps.steps_unconverged = I.st.steps_unconverged;
+    ps.outer_max = I.st.outer_max;
+    ps.pcur = I.s.pcur;
+    sweeps0[i] = I.st.sweeps_total;
+  }
+  HCK(s, hipMemcpyAsync(s->pitems_d, s->pitems_h, sizeof(PItem) * n, hipMemcpyHostToDevice, s->stream));
+  HCK(s, hipMemcpyAsync(s->pstats_d, s->pstats_h, sizeof(PStats) * n, hipMemcpyHostToDevice, s->stream));
+  HCK(s, hipMemsetAsync(s->pbar_d, 0, sizeof(unsigned) * n, s->stream));
+  HCK(s, hipMemsetAsync(s->perr_d, 0, sizeof(int), s->stream));
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (s->timing) {
+    HCK(s, hipEventCreate(&ea));
+    HCK(s, hipEventCreate(&eb));
+    HCK(s, hipEventRecord(ea, s->stream));
+  }
+  HCK(s, launch_persistent(s->stream, f32, s->pitems_d, s->pslots_d, s->persist_blocks, nsteps, s->perr_d,
+                           s->persist_limit));
+  if (s->timing) HCK(s, hipEventRecord(eb, s->stream));
+  HCK(s, hipMemcpyAsync(s->pstats_h, s->pstats_d, sizeof(PStats) * n, hipMemcpyDeviceToHost, s->stream));
+  HCK(s, hipMemcpyAsync(s->perr_h, s->perr_d, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HCK(s, hipStreamSynchronize(s->stream));
+  bool nonfinite = false;
+  double sweep_ms = 0.0;
+  long long sweep_bytes = 0;
+  for (int i = 0; i < n; i++) {
+    Inst& I = s->in[i];
+    const PStats& ps = s->pstats_h[i];
+    I.st.t = ps.t;
+    I.st.dt_last = ps.dt_last;
+    I.st.res_last = ps.res_last;
+    I.st.sweeps_total = ps.sweeps_total;
+    I.st.steps = ps.steps;
+    I.st.sweeps_max = ps.sweeps_max;
+    I.st.steps_unconverged = ps.steps_unconverged;
+    I.st.outer_max = ps.outer_max;
+    I.s.pcur = ps.pcur;
+    nonfinite |= ps.nonfinite != 0;
+    sweep_ms = std::max(sweep_ms, ps.sweep_ticks / s->clock_khz);
+    sweep_bytes += (long long)(f32 ? 12 : 24) * I.g.nx * I.g.ny * I.g.nz * (ps.sweeps_total - sweeps0[i]);
+  }
+  if (s->timing) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ea, eb) == hipSuccess) {
+      s->tm.ms[NS_T_SOR] += std::min((double)ms, sweep_ms);
+      s->tm.ms[NS_T_OTHER] += std::max(0.0, (double)ms - sweep_ms);
+      s->tm.launches[NS_T_SOR] += 1;
+      s->tm.sor_bytes += sweep_bytes;
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+  }
+  if (*s->perr_h) return fail(s, NS_E_DEVICE, "persistent batch: a team barrier wait exceeded its time limit");
+  if (nonfinite) return fail(s, NS_E_NONFINITE, "non-finite residual in the pressure solve");
+  return NS_OK;
+}
+
 ns_status copy_in(ns_solver* s, Inst& I, void* dst, bool dst_f32, const double* src, int on_device) {
   const long n = I.g.ntot;
   hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -1469,7 +1708,11 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
             hipSuccess ||
         hipMalloc((void**)&s->stage_d, sizeof(StageItem) * kStageKinds * n_instances) != hipSuccess)
       return bail(NS_E_OOM, "batch table allocation failed");
-    if (params[0].tile[0] > 0) {
+    if (persist_setup(s) != NS_OK) return bail(NS_E_DEVICE, "persistent launch set-up: " + s->err);
+    if (s->persist) {
+      s->batch_ty = 16;
+      s->batch_zc = 0;
+    } else if (params[0].tile[0] > 0) {
       s->batch_ty = params[0].tile[0];
       s->batch_zc = params[0].tile[1];
       if (s->batch_ty >= 16)
@@ -1578,6 +1821,12 @@ ns_status ns_step(ns_solver* s, int32_t nsteps, ns_stats* stats) {
     }
     return save_state(s, I, I.s, I.ck[slot]);
   };
+  if (s->batched && s->persist) {
+    ret = nsteps > 0 ? persist_run(s, nsteps) : NS_OK;
+    if (stats)
+      for (size_t i = 0; i < s->in.size(); i++) stats[i] = s->in[i].st;
+    return ret;
+  }
   for (int n = 0; n < nsteps && ret == NS_OK; n++) {
     if (s->batched) {
       for (auto& I : s->in)
@@ -1724,6 +1973,14 @@ void ns_destroy(ns_solver* s) {
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
   (void)hipFree(s->ctl_all);
   (void)hipFree(s->stage);
+  if (s->pitems_h) (void)hipHostFree(s->pitems_h);
+  if (s->pstats_h) (void)hipHostFree(s->pstats_h);
+  if (s->perr_h) (void)hipHostFree(s->perr_h);
+  (void)hipFree(s->pitems_d);
+  (void)hipFree(s->pstats_d);
+  (void)hipFree(s->pslots_d);
+  (void)hipFree(s->pbar_d);
+  (void)hipFree(s->perr_d);
   delete s;
 }
 

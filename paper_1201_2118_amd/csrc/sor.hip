@@ -14,6 +14,7 @@
 // workgroup of the red pass applies the stop rule and raises ctl->done.
 #include <hip/hip_runtime.h>
 
+#include "cells.h"
 #include "ns_internal.h"
 #include "reduce.h"
 
@@ -27,37 +28,6 @@ inline int grid_for(long n, int cap = 8192) {
   long b = (n + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
   return (int)(b < cap ? b : cap);
-}
-
-// Neighbour offsets and coefficients of cell (i, j, k): a missing neighbour
-// (wall) gets coefficient 0 and points at the cell itself so that the load
-// stays in bounds and finite.
-struct Nb {
-  long o[6];
-  double a[6];
-  double ac;
-};
-
-__device__ __forceinline__ Nb neighbours(const Geo& g, int i, int j, int k) {
-  Nb n;
-  const int sz[3] = {g.nx, g.ny, g.nz};
-  const int id[3] = {i, j, k};
-  const long st[3] = {1, g.sx, g.sxy};
-  const double h2[3] = {g.idx2, g.idy2, g.idz2};
-  n.ac = 0.0;
-#pragma unroll
-  for (int d = 0; d < 3; d++) {
-    // minus side
-    if (id[d] > 1) { n.o[2 * d] = -st[d]; n.a[2 * d] = h2[d]; }
-    else if (g.per[d]) { n.o[2 * d] = (long)(sz[d] - 1) * st[d]; n.a[2 * d] = h2[d]; }
-    else { n.o[2 * d] = 0; n.a[2 * d] = 0.0; }
-    // plus side
-    if (id[d] < sz[d]) { n.o[2 * d + 1] = st[d]; n.a[2 * d + 1] = h2[d]; }
-    else if (g.per[d]) { n.o[2 * d + 1] = -(long)(sz[d] - 1) * st[d]; n.a[2 * d + 1] = h2[d]; }
-    else { n.o[2 * d + 1] = 0; n.a[2 * d + 1] = 0.0; }
-    n.ac += n.a[2 * d] + n.a[2 * d + 1];
-  }
-  return n;
 }
 
 struct Cell {
@@ -138,77 +108,6 @@ k_sor_black(const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restri
     for (int q = 0; q < 6; q++) s += nb.a[q] * ((double)p_out[cl.c + nb.o[q]] - pc);
     const double r = s - (double)rhs[cl.c];
     p_out[cl.c] = T(pc + omega * r / nb.ac);
-  }
-}
-
-// Mixed-precision outer step: p_out = p_in + e, r = rhs - A p_out (FP64
-// arithmetic, stored as FP32), RMS of the FP64 r into ctl->res; decides
-// outer convergence and sets the inner threshold eta * RMS(r).
-// HAS_E: p_out = p_in + e is formed and stored (e non-null); else p = p_in.
-// A compile-time choice, so the loop body carries no per-load branch and
-// its loads can be in flight together.
-template <bool HAS_E>
-__device__ __forceinline__ void defect_cells(const Geo& g, int zr, const CellBlk& blk,
-                                             const double* __restrict__ p_in, const float* __restrict__ e,
-                                             double* __restrict__ p_out, const float* __restrict__ rhs,
-                                             float* __restrict__ r, Ctl* ctl, double* part, double eta, double* sh,
-                                             int* sh_last) {
-  const long n = (long)g.nx * g.ny * g.nz;
-  double acc = 0.0;
-  // A thread marches its (i, j) column through a run of zr planes and keeps
-  // p + e of the planes below, at and above the cell in registers.
-  const int i = blk.x * kCellX + threadIdx.x + 1;
-  const int j = blk.y * kCellY + threadIdx.y + 1;
-  if (i <= g.nx && j <= g.ny) {
-    const Nb nb = neighbours(g, i, j, 1);  // x and y entries; z per plane below
-    const int k0 = blk.z * zr + 1;
-    const int k1 = min(g.nz, k0 + zr - 1);
-    auto q = [&](long c) {
-      if constexpr (HAS_E)
-        return p_in[c] + (double)e[c];
-      else
-        return p_in[c] + 0.0;
-    };
-    const int per2 = g.per[2];
-    auto zdn = [&](int k) -> long { return k > 1 ? -g.sxy : (per2 ? (long)(g.nz - 1) * g.sxy : 0L); };
-    auto zup = [&](int k) -> long { return k < g.nz ? g.sxy : (per2 ? -(long)(g.nz - 1) * g.sxy : 0L); };
-    long c = (long)k0 * g.sxy + (long)j * g.sx + i;
-    double qc = q(c), qd = q(c + zdn(k0));
-    // two planes per trip: the loads of the second are issued with those of
-    // the first (measured 5 % faster than one, and faster than four)
-#pragma unroll 2
-    for (int k = k0; k <= k1; k++, c += g.sxy) {
-      const double qu = q(c + zup(k));
-      const double azm = (k > 1 || per2) ? g.idz2 : 0.0;
-      const double azp = (k < g.nz || per2) ? g.idz2 : 0.0;
-      double s = 0.0;
-#pragma unroll
-      for (int t = 0; t < 4; t++) s += nb.a[t] * (q(c + nb.o[t]) - qc);
-      s += azm * (qd - qc);
-      s += azp * (qu - qc);
-      const double rr = (double)rhs[c] - s;
-      r[c] = (float)rr;
-      acc += rr * rr;
-      if constexpr (HAS_E) p_out[c] = qc;
-      qd = qc;
-      qc = qu;
-    }
-  }
-  double s = block_sum(acc, sh);
-  if (publish_partial(part, blk.id, s, ctl, blk.count, sh_last)) {
-    double tot = sum_partials(part, blk.count, sh);
-    if (flat_tid() == 0) {
-      // an identically zero rhs needs no correction at all
-      const double res = ctl->rhs_rms == 0.0 ? 0.0 : sqrt(tot / (double)n);
-      const bool fin = isfinite(res);
-      ctl->res = res;
-      ctl->outer_done = !(res > ctl->thr) || !fin;
-      if (!fin) ctl->nonfinite = 1;
-      ctl->thr_in = eta * res;
-      ctl->done = ctl->outer_done;
-      ctl->final_ = 0;
-      ctl->ticket = 0;
-    }
   }
 }
 

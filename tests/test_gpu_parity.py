@@ -193,7 +193,8 @@ def test_batched_instances_match_standalone_runs_and_oracle(form, tile):
         sc = U.velocity_scale(ref, prm)
         # different sweep shapes round differently (FP32 arithmetic in the
         # mixed correction sweeps)
-        same = (1e-12 if tile and tile[0] >= 16 else 1e-13) if form == "fp64" else 1e-6
+        # (the default shape is the persistent launch: two-sweep pass tiles)
+        same = (1e-12 if tile is None or tile[0] >= 16 else 1e-13) if form == "fp64" else 1e-6
         for c, f in enumerate("uvw"):
             assert U.vel_rel(s.get_np(f, i), ref[c], m[c], sc) < same, (i, f)
         o, _ = U.oracle_run(dict(prm, precision="fp64"), 3, mode=0 if form == "fp64" else 1)
@@ -204,24 +205,30 @@ def test_batched_instances_match_standalone_runs_and_oracle(form, tile):
 
 def test_batched_workload_runs():
     """The 64-cavity workload (sizes U{24..96}, Re U[50, 1000], adaptive dt,
-    mixed precision), a few steps: every instance advances and stays
-    finite; two instances are checked against standalone runs."""
+    mixed precision) in the persistent launch, two steps: every instance
+    equals its standalone run (same sweep counts, velocity to 1e-6 of its
+    scale: the sweep shapes round differently in FP32)."""
     prms, _ = W.batched_64()
     prms = [dict(p, precision="mixed") for p in prms]
     from paper_1201_2118_amd.solver import Solver
     s = Solver(prms)
     s.step(2)
+    worst = 0.0
     for i in range(len(prms)):
         st = s.stats(i)
         assert st["steps"] == 2 and st["dt_last"] > 0 and np.isfinite(st["res_last"])
-    for i in (0, 41):
         one = U.gpu_run(prms[i], 2)
-        assert s.stats(i)["sweeps_total"] == one.stats()["sweeps_total"]
+        assert st["sweeps_total"] == one.stats()["sweeps_total"], i
+        assert st["t"] == one.stats()["t"], i
         m = U.masks(prms[i])
         ref = [one.get_np(f) for f in "uvw"]
         sc = U.velocity_scale(ref, prms[i])
         for c, f in enumerate("uvw"):
-            assert U.vel_rel(s.get_np(f, i), ref[c], m[c], sc) < 1e-6, (i, f)
+            e = U.vel_rel(s.get_np(f, i), ref[c], m[c], sc)
+            worst = max(worst, e)
+            assert e < 1e-6, (i, f, e)
+        one.close()
+    print(f"64 cavities, 2 steps: worst velocity difference to the standalone runs {worst:.2e}", flush=True)
 
 
 def test_nonfinite_state_is_reported():

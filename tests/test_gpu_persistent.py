@@ -1,0 +1,118 @@
+"""The persistent batched launch: every step of every domain of a batched
+handle in one cooperative launch, teams of workgroups per domain with
+device-side barriers and stop rules.
+
+* it is one launch per ns_step call (stage timers of a timed handle);
+* it equals the multi-launch batched path (NS_BATCH_LAUNCHES: one launch
+  per stage and per pass, host-polled) and each standalone run, FP64 and
+  mixed, on domains with walls, periodic axes, adaptive dt and body force;
+* a NaN in one domain is reported as NS_E_NONFINITE;
+* a barrier wait that exceeds its limit (forced from the host with a zero
+  limit) raises the device error flag, every workgroup returns, and the
+  call reports NS_E_DEVICE; the device stays usable.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import nsworkloads as W
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _domains(form):
+    prms = [W.cavity(10, ny=12, nz=8), W.cavity(16, re=300.0, dt=0.004), W.periodic_box(8, nz=6, dt=1e-3),
+            W.cavity(37, ny=25, nz=30, re=700.0, dt=0.0, tau=0.5), W.cavity(61, ny=9, nz=14, re=90.0, dt=0.0),
+            W.cavity(24, ny=40, nz=20, re=200.0, dt=0.003)]
+    prms[5]["bc"] = (0, 1, 0)
+    prms[1]["g"] = (0.0, 0.3, -0.1)
+    return [dict(p, precision=form) for p in prms]
+
+
+def test_persistent_is_one_launch_per_call():
+    from paper_1201_2118_amd import abi
+    from paper_1201_2118_amd.solver import Solver
+    prms = _domains("mixed")
+    s = Solver([dict(p, flags=abi.NS_TIMING if i == 0 else 0) for i, p in enumerate(prms)])
+    s.step(3)
+    t = s.timing()
+    assert t.launches[abi.NS_T_SOR] == 1
+    for k in (abi.NS_T_BC, abi.NS_T_FGH, abi.NS_T_RHS, abi.NS_T_DEFECT, abi.NS_T_PROJECT):
+        assert t.launches[k] == 0, k
+    assert all(s.stats(i)["steps"] == 3 for i in range(len(prms)))
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_persistent_equals_multilaunch_and_standalone(form):
+    from paper_1201_2118_amd import abi
+    from paper_1201_2118_amd.solver import Solver
+    prms = _domains(form)
+    fx, fy, fz = W.gaussian_velocity(prms[1], 0.2, 19)
+    a = Solver(prms)
+    b = Solver([dict(p, flags=abi.NS_BATCH_LAUNCHES) for p in prms])
+    for s in (a, b):
+        for name, arr in zip(("fx", "fy", "fz"), (fx, fy, fz)):
+            s.set(name, arr, inst=1)
+        s.step(2)
+        s.step(1)
+    for i, prm in enumerate(prms):
+        sa, sb = a.stats(i), b.stats(i)
+        assert sa["sweeps_total"] == sb["sweeps_total"], (i, sa, sb)
+        assert sa["steps"] == sb["steps"] == 3 and sa["t"] == sb["t"]
+        assert sa["outer_max"] == sb["outer_max"]
+        one = U.gpu_run(prm, 0)
+        if i == 1:
+            for name, arr in zip(("fx", "fy", "fz"), (fx, fy, fz)):
+                one.set(name, arr)
+        one.step(3)
+        assert sa["sweeps_total"] == one.stats()["sweeps_total"], i
+        m = U.masks(prm)
+        ref = [one.get_np(f) for f in "uvw"]
+        sc = U.velocity_scale(ref, prm)
+        bar = 1e-12 if form == "fp64" else 1e-6
+        for c, f in enumerate("uvw"):
+            assert U.vel_rel(a.get_np(f, i), b.get_np(f, i), m[c], sc) < bar, (i, f)
+            assert U.vel_rel(a.get_np(f, i), ref[c], m[c], sc) < bar, (i, f)
+        if form == "fp64":
+            assert U.pressure_rel(a.get_np("p", i), one.get_np("p"), m[3]) < 1e-12, i
+        one.close()
+
+
+def test_persistent_reports_nonfinite():
+    from paper_1201_2118_amd import abi
+    from paper_1201_2118_amd.solver import Solver
+    prms = _domains("mixed")
+    s = Solver(prms)
+    init = U.random_state(prms[3], 4)
+    init["u"][5, 5, 5] = np.nan
+    for name, arr in init.items():
+        s.set(name, arr, inst=3)
+    assert s.step(2, check=False) == abi.NS_E_NONFINITE
+    assert "non-finite" in s.last_error()
+    assert s.stats(3)["steps"] == 0
+    assert s.stats(0)["steps"] == 2
+
+
+def test_persistent_barrier_wait_gives_up():
+    """A zero wait limit (read when the handle is created) makes the first
+    barrier that has to wait give up: the error flag stops every team, the
+    launch ends normally and ns_step reports NS_E_DEVICE."""
+    from paper_1201_2118_amd import abi
+    from paper_1201_2118_amd.solver import Solver
+    prms, _ = W.batched_64(count=8)
+    prms = [dict(p, precision="mixed") for p in prms]
+    os.environ["NS_TEAM_WAIT_LIMIT_US"] = "0"
+    try:
+        s = Solver(prms)
+    finally:
+        del os.environ["NS_TEAM_WAIT_LIMIT_US"]
+    code = s.step(1, check=False)
+    assert code == abi.NS_E_DEVICE, code
+    assert "time limit" in s.last_error()
+    s.close()
+    # the device and a fresh handle work as before
+    s = Solver(prms)
+    s.step(1)
+    assert all(s.stats(i)["steps"] == 1 for i in range(len(prms)))
