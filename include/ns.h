@@ -77,8 +77,10 @@ enum { NS_FP64 = 0, NS_MIXED = 1 };
 enum {
   NS_ALLOW_UNSTABLE = 1, /* accept a fixed dt beyond the stability bounds */
   NS_TIMING = 2,         /* record per-stage GPU times (ns_get_timing) */
-  NS_BATCH_LAUNCHES = 4  /* several instances (flag of instance 0): one launch per stage and per
+  NS_BATCH_LAUNCHES = 4, /* several instances (flag of instance 0): one launch per stage and per
                             pass of sweeps, polled by the host, instead of the persistent launch */
+  NS_GENERATED = 8       /* one instance: the predictor and the projection are the kernels the
+                            build generates from the kernel descriptors (same results) */
 };
 
 typedef struct {

@@ -2,7 +2,8 @@
 
     python -m paper_1201_2118_amd.build
 
-Sources: paper_1201_2118_amd/csrc/*.hip; public header: include/ns.h.
+Sources: paper_1201_2118_amd/csrc/*.hip; public header: include/ns.h; kernels
+generated from descriptors/kernels.ccl go to _build/gen first.
 Objects go to _build/ (not shipped); the library lands next to this file.
 """
 from __future__ import annotations
@@ -18,9 +19,10 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libns.so")
+GEN = os.path.join(BUILD, "gen")
 
-SOURCES = ["kernels.hip", "sor.hip", "sor_fused.hip", "sor_pass.hip", "persist.hip", "adjoint.hip",
-           "runtime.hip"]
+SOURCES = ["kernels.hip", "sor.hip", "sor_fused.hip", "sor_pass.hip", "persist.hip", "generated.hip",
+           "adjoint.hip", "runtime.hip"]
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -40,7 +42,7 @@ def hipcc() -> str:
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + HIPFLAGS + ["-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc()] + HIPFLAGS + ["-I", INCLUDE, "-I", CSRC, "-I", GEN, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -51,8 +53,21 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+def generate(verbose: bool = False) -> list:
+    """Write the kernels declared in descriptors/kernels.ccl as HIP headers
+    into _build/gen (the kernel-descriptor layer; generated.hip includes
+    them)."""
+    from .descriptors import ccl
+    paths = ccl.build(ccl.DESCRIPTOR, GEN)
+    if verbose:
+        for p in paths:
+            print("generated", p, flush=True)
+    return paths
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    generate(verbose)
     srcs = list(SOURCES)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))

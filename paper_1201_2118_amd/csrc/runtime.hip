@@ -17,6 +17,7 @@
 #include <string>
 #include <vector>
 
+#include "generated.h"
 #include "ns.h"
 #include "ns_internal.h"
 
@@ -222,7 +223,7 @@ ns_status validate(const ns_params& p, int idx) {
       if (!std::isfinite(p.wall_vel[f][c])) return bad("wall velocities must be finite");
   for (int c = 0; c < 3; c++)
     if (!std::isfinite(p.g[c])) return bad("body force must be finite");
-  if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING | NS_BATCH_LAUNCHES)) return bad("unknown flag bits");
+  if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING | NS_BATCH_LAUNCHES | NS_GENERATED)) return bad("unknown flag bits");
   if (!(p.tile[0] == -1 || p.tile[0] == 0 || p.tile[0] == 4 || p.tile[0] == 8 || p.tile[0] == 12 ||
         p.tile[0] == 16 || p.tile[0] == 24 || p.tile[0] == 32))
     return bad("tile[0] must be -1, 0, 4, 8, 12, 16, 24 or 32");
@@ -733,8 +734,12 @@ ns_status step_pre(ns_solver* s, int idx, State& S) {
   }
   {
     Timed t(s, NS_T_FGH);
-    HCK(s, launch_fgh<T>(s->stream, g, u, v, w, (const T*)I.frc[0], (const T*)I.frc[1], (const T*)I.frc[2],
-                         (T*)I.F, (T*)I.G, (T*)I.H, I.ctl, p.re, p.gamma, p.g));
+    if (p.flags & NS_GENERATED)
+      HCK(s, launch_gen_fgh<T>(s->stream, g, u, v, w, (const T*)I.frc[0], (const T*)I.frc[1], (const T*)I.frc[2],
+                               (T*)I.F, (T*)I.G, (T*)I.H, I.ctl, p.re, p.gamma, p.g));
+    else
+      HCK(s, launch_fgh<T>(s->stream, g, u, v, w, (const T*)I.frc[0], (const T*)I.frc[1], (const T*)I.frc[2],
+                           (T*)I.F, (T*)I.G, (T*)I.H, I.ctl, p.re, p.gamma, p.g));
   }
   {
     Timed t(s, NS_T_RHS);
@@ -777,8 +782,12 @@ ns_status step_post(ns_solver* s, int idx, State& S, int sweeps, int outer, bool
   {
     Timed t(s, NS_T_PROJECT);
     HCK(s, launch_p_ghosts<double>(s->stream, g, S.p[S.pcur]));
-    HCK(s, launch_project<T>(s->stream, g, (const T*)I.F, (const T*)I.G, (const T*)I.H, S.p[S.pcur], u, v, w,
-                             I.ctl, 0.0));
+    if (p.flags & NS_GENERATED)
+      HCK(s, launch_gen_project<T>(s->stream, g, (const T*)I.F, (const T*)I.G, (const T*)I.H, S.p[S.pcur], u, v,
+                                   w, I.ctl));
+    else
+      HCK(s, launch_project<T>(s->stream, g, (const T*)I.F, (const T*)I.G, (const T*)I.H, S.p[S.pcur], u, v, w,
+                               I.ctl, 0.0));
   }
   {
     Timed t(s, NS_T_BC);
@@ -1620,6 +1629,8 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
   for (int i = 0; i < n_instances; i++) {
     ns_status st = validate(params[i], i);
     if (st != NS_OK) return st;
+    if ((params[i].flags & NS_GENERATED) && n_instances > 1)
+      return fail(nullptr, NS_E_INVALID, "NS_GENERATED needs a handle of one instance");
   }
   ns_solver* s = new ns_solver();
   if (hipGetDevice(&s->device) != hipSuccess) {
