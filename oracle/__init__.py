@@ -48,6 +48,7 @@ class _Cfg(ctypes.Structure):
         ("wall", (ctypes.c_double * 3) * 6),
         ("g", ctypes.c_double * 3),
         ("eta", ctypes.c_double),
+        ("advective", ctypes.c_int),
     ]
 
 
@@ -139,6 +140,7 @@ class Oracle:
         for q in range(3):
             c.g[q] = float(g[q])
         c.eta = float(params.get("eta", 1e-2))
+        c.advective = 1 if params.get("convection", "conservative") == "advective" else 0
         self.cfg = c
         self.shape = (c.nz + 2, c.ny + 2, c.nx + 2)
         self.u, self.v, self.w, self.p = (np.zeros(self.shape) for _ in range(4))
@@ -277,8 +279,11 @@ def gradient(params: dict, u0, v0, w0, target, nsteps: int):
     """dL/du0 for L = 1/2 sum over the unknowns of (u^N - target)^2, by the
     reverse sweep: lambda^N = u^N - target, then for n = N-1..0
     mu = P lambda^{n+1} (transpose of the exact projection) and
-    lambda^n = B^T J_Phi(u^n)^T mu.  Fixed dt only.  The forward keeps every
-    state (no checkpointing needed at oracle sizes)."""
+    lambda^n = B^T J_Phi(u^n)^T mu.  Fixed dt only; the conservative form of
+    the convective term only (the transpose is written for it).  The forward
+    keeps every state (no checkpointing needed at oracle sizes)."""
+    if params.get("convection", "conservative") != "conservative":
+        raise ValueError("the oracle adjoint covers the conservative convective form only")
     o = Oracle(params)
     o.set("u", u0); o.set("v", v0); o.set("w", w0)
     o.bc_vel()

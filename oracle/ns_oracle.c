@@ -152,6 +152,20 @@ static double psi(double t, double a, double b, double gamma) {
   return t * (a + b) / 2.0 + gamma * fabs(t) * (a - b) / 2.0;
 }
 
+/* The other form of the lineage the paper follows (Hirt's SOLA family and
+ * NASA-VOF2D): the convective term in advective form, (u.grad)u_c =
+ * sum_d a_d dq/dx_d, with a_d the d-velocity at the unknown's own position
+ * (the unknown itself for d == c, else the mean of the four d-faces around
+ * it: at pos and pos + e_c, on both sides in d) and the derivative an
+ * alpha-weighted blend of the backward and forward differences:
+ *     a (dq/dx)_h = a [ (1 + alpha s)(q - q[-d]) + (1 - alpha s)(q[+d] - q) ] / (2 h)
+ * with s = sign(a), sign(0) = 0 (alpha = 0: central; alpha = 1: upwind).
+ * Selected by cfg->advective with alpha = cfg->gamma.                     */
+static double adv_term(double a, double qm, double qc, double qp, double alpha, double h) {
+  double s = (a > 0.0) - (a < 0.0);
+  return a * ((1.0 + alpha * s) * (qc - qm) + (1.0 - alpha * s) * (qp - qc)) / (2.0 * h);
+}
+
 static long stride(const nso_cfg *c, int a) { return a == 0 ? 1 : (a == 1 ? SX : SX * SY); }
 
 void nso_fgh(const nso_cfg *c, double dt, const double *u, const double *v,
@@ -183,6 +197,11 @@ void nso_fgh(const nso_cfg *c, double dt, const double *u, const double *v,
             double qp = q[id + sd], qm = q[id - sd];
             lap += (qp - 2.0 * qc + qm) / (h * h);
             const double *T = vel[d];
+            if (c->advective) {
+              double a = d == comp ? qc : (T[id] + T[id + sc] + T[id - sd] + T[id - sd + sc]) / 4.0;
+              conv += adv_term(a, qm, qc, qp, c->gamma, h);
+              continue;
+            }
             double thi = (T[id] + T[id + sc]) / 2.0;
             double tlo = (T[id - sd] + T[id - sd + sc]) / 2.0;
             conv += (psi(thi, qc, qp, c->gamma) - psi(tlo, qm, qc, c->gamma)) / h;

@@ -50,6 +50,8 @@ typedef struct {
   double wall[6][3];    /* wall velocity on faces -x,+x,-y,+y,-z,+z */
   double g[3];          /* constant body force */
   double eta;           /* defect-correction inner tolerance factor */
+  int advective;        /* 0: conservative fluxes blended by gamma; 1: advective form
+                           weighted by alpha = gamma (see nso_fgh) */
 } nso_cfg;
 
 typedef struct {

@@ -25,8 +25,8 @@ def _sample(prm, key, comp, nu):
     return np.broadcast_to(_FN[key](X, Y, Z, nu), X.shape).astype(np.float64).copy()
 
 
-def _setup(n, re, gamma, **kw):
-    prm = W.cavity(n, lid=0.0, re=re, gamma=gamma, **kw)
+def _setup(n, re, gamma, convection="conservative", **kw):
+    prm = dict(W.cavity(n, lid=0.0, re=re, gamma=gamma, **kw), convection=convection)
     nu = 1.0 / re
     o = oracle.Oracle(prm)
     u, v, w = (_sample(prm, k, c, nu) for c, k in enumerate("uvw"))
@@ -35,10 +35,10 @@ def _setup(n, re, gamma, **kw):
     return prm, o, (u, v, w), p
 
 
-def _momentum_truncation(n, gamma):
+def _momentum_truncation(n, gamma, convection="conservative"):
     """max over unknowns of (F - u)/dt - G_h p at the exact solution: the
     local truncation error of the momentum predictor (walls included)."""
-    prm, o, (u, v, w), p = _setup(n, 1.0, gamma)
+    prm, o, (u, v, w), p = _setup(n, 1.0, gamma, convection)
     o.bc_vel(u, v, w)
     dt = 1e-3
     F, G, H = o.fgh(dt, u, v, w)
@@ -52,8 +52,13 @@ def _momentum_truncation(n, gamma):
     return err
 
 
-def test_momentum_truncation_second_order_central():
-    e = [_momentum_truncation(n, 0.0) for n in (16, 32, 64)]
+FORMS = ["conservative", "advective"]
+
+
+@pytest.mark.parametrize("convection", FORMS)
+def test_momentum_truncation_second_order_central(convection):
+    """gamma (conservative) or alpha (advective) = 0: second order."""
+    e = [_momentum_truncation(n, 0.0, convection) for n in (16, 32, 64)]
     for k in range(2):
         assert 3.6 < e[k] / e[k + 1] < 4.4, e
 
@@ -66,8 +71,18 @@ def test_momentum_truncation_first_order_donor_cell():
     assert 1.4 < e[1] / e[2] < 2.6, e
 
 
-def _steady_error(n):
-    prm, o, (u, v, w), p = _setup(n, 1.0, 0.0, tol=1e-12, itermax=20000)
+def test_momentum_truncation_first_order_advective_upwind():
+    """The advective form with alpha = 1 (full upwind): observed order near
+    1 (second order would give 2); the first-order term comes out of the
+    second-order one only past n = 64 on this solution."""
+    ns = (64, 128, 192)
+    e = [_momentum_truncation(n, 1.0, "advective") for n in ns]
+    orders = [np.log(e[k] / e[k + 1]) / np.log(ns[k + 1] / ns[k]) for k in range(2)]
+    assert all(0.7 < q < 1.3 for q in orders), (e, orders)
+
+
+def _steady_error(n, convection="conservative"):
+    prm, o, (u, v, w), p = _setup(n, 1.0, 0.0, convection, tol=1e-12, itermax=20000)
     h = 1.0 / n
     prm["dt"] = 0.9 * h * h / 6.0
     o = oracle.Oracle(prm)
@@ -83,9 +98,10 @@ def _steady_error(n):
     return float(np.abs(o.u[m] - u[m]).max())
 
 
-def test_steady_manufactured_solution_second_order():
+@pytest.mark.parametrize("convection", FORMS)
+def test_steady_manufactured_solution_second_order(convection):
     """Run the full step (walls, forcing, SOR, projection) to its steady
     state; the distance to the exact solution falls by about 4 per halving
-    of h (gamma = 0)."""
-    e8, e16 = _steady_error(8), _steady_error(16)
+    of h (gamma / alpha = 0)."""
+    e8, e16 = _steady_error(8, convection), _steady_error(16, convection)
     assert 3.3 < e8 / e16 < 4.7, (e8, e16)
