@@ -79,8 +79,11 @@ enum {
   NS_TIMING = 2,         /* record per-stage GPU times (ns_get_timing) */
   NS_BATCH_LAUNCHES = 4, /* several instances (flag of instance 0): one launch per stage and per
                             pass of sweeps, polled by the host, instead of the persistent launch */
-  NS_GENERATED = 8       /* one instance: the predictor and the projection are the kernels the
+  NS_GENERATED = 8,      /* one instance: the predictor and the projection are the kernels the
                             build generates from the kernel descriptors (same results) */
+  NS_ADVECTIVE = 16      /* one instance: the convective term in advective form weighted by
+                            alpha = gamma (SOLA / NASA-VOF2D) instead of conservative fluxes
+                            blended by gamma; not with NS_GENERATED or checkpoint_every */
 };
 
 typedef struct {
@@ -90,7 +93,7 @@ typedef struct {
   double re;              /* Reynolds number; nu = 1 / re (rho = 1, phi = p) */
   double dt;              /* > 0: fixed step; <= 0: adaptive with tau */
   double tau;             /* adaptive safety factor in (0, 1] */
-  double gamma;           /* donor-cell blend in [0, 1] */
+  double gamma;           /* donor-cell blend in [0, 1] (NS_ADVECTIVE: the upwind weight alpha) */
   double omega;           /* SOR relaxation in (0, 2) */
   double tol;             /* stop when RMS residual <= tol * RMS(rhs) */
   int32_t itermax;        /* SOR sweeps per step (mixed: inner sweeps in total) */

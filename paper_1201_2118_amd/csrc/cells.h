@@ -96,6 +96,72 @@ __device__ __forceinline__ void fgh_cells(const Geo& g, int zr, const CellBlk& b
   });
 }
 
+// The advective form of the convective term (the SOLA / NASA-VOF2D form):
+// sum_d a_d dq/dx_d, with a_d the d-velocity at the unknown's position (the
+// unknown itself along its own axis, else the mean of the four d-faces
+// around it) and the derivative an alpha-weighted blend of the backward and
+// forward differences: a [(1 + alpha s)(q - q[-d]) + (1 - alpha s)(q[+d] - q)] / (2 h),
+// s = sign(a) with sign(0) = 0 (alpha 0: central, 1: upwind).
+__device__ __forceinline__ double adv_d(double a, double qm, double qc, double qp, double alpha, double ih) {
+  const double s = (double)((a > 0.0) - (a < 0.0));
+  return a * ((1.0 + alpha * s) * (qc - qm) + (1.0 - alpha * s) * (qp - qc)) * (0.5 * ih);
+}
+
+// Predictor with the advective form (alpha in place of gamma); otherwise as
+// fgh_cells.
+template <class T, bool HAS_F>
+__device__ __forceinline__ void fgh_adv_cells(const Geo& g, int zr, const CellBlk& blk, const T* __restrict__ u,
+                                              const T* __restrict__ v, const T* __restrict__ w,
+                                              const T* __restrict__ fx, const T* __restrict__ fy,
+                                              const T* __restrict__ fz, T* __restrict__ F, T* __restrict__ G,
+                                              T* __restrict__ H, const Ctl* __restrict__ ctl, double nu,
+                                              double alpha, double gx, double gy, double gz) {
+  const double dt = ctl->dt;
+  const long sx = g.sx, sxy = g.sxy;
+  for_cells<2>(g, zr, blk, [&](int ci, int cj, int ck, long c) {
+    double Fv, Gv, Hv;
+    {  // F on the x face i
+      const double q = u[c], qe = u[c + 1], qw = u[c - 1], qn = u[c + sx], qs = u[c - sx],
+                   qt = u[c + sxy], qb = u[c - sxy];
+      const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
+                         (qt - 2.0 * q + qb) * g.idz2;
+      const double ay = 0.25 * ((double)v[c] + (double)v[c + 1] + (double)v[c - sx] + (double)v[c - sx + 1]);
+      const double az = 0.25 * ((double)w[c] + (double)w[c + 1] + (double)w[c - sxy] + (double)w[c - sxy + 1]);
+      const double conv = adv_d(q, qw, q, qe, alpha, g.idx) + adv_d(ay, qs, q, qn, alpha, g.idy) +
+                          adv_d(az, qb, q, qt, alpha, g.idz);
+      const double f = gx + (HAS_F ? (double)fx[c] : 0.0);
+      Fv = q + dt * (nu * lap - conv + f);
+    }
+    {  // G on the y face j
+      const double q = v[c], qe = v[c + 1], qw = v[c - 1], qn = v[c + sx], qs = v[c - sx],
+                   qt = v[c + sxy], qb = v[c - sxy];
+      const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
+                         (qt - 2.0 * q + qb) * g.idz2;
+      const double ax = 0.25 * ((double)u[c] + (double)u[c + sx] + (double)u[c - 1] + (double)u[c - 1 + sx]);
+      const double az = 0.25 * ((double)w[c] + (double)w[c + sx] + (double)w[c - sxy] + (double)w[c - sxy + sx]);
+      const double conv = adv_d(ax, qw, q, qe, alpha, g.idx) + adv_d(q, qs, q, qn, alpha, g.idy) +
+                          adv_d(az, qb, q, qt, alpha, g.idz);
+      const double f = gy + (HAS_F ? (double)fy[c] : 0.0);
+      Gv = q + dt * (nu * lap - conv + f);
+    }
+    {  // H on the z face k
+      const double q = w[c], qe = w[c + 1], qw = w[c - 1], qn = w[c + sx], qs = w[c - sx],
+                   qt = w[c + sxy], qb = w[c - sxy];
+      const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
+                         (qt - 2.0 * q + qb) * g.idz2;
+      const double ax = 0.25 * ((double)u[c] + (double)u[c + sxy] + (double)u[c - 1] + (double)u[c - 1 + sxy]);
+      const double ay = 0.25 * ((double)v[c] + (double)v[c + sxy] + (double)v[c - sx] + (double)v[c - sx + sxy]);
+      const double conv = adv_d(ax, qw, q, qe, alpha, g.idx) + adv_d(ay, qs, q, qn, alpha, g.idy) +
+                          adv_d(q, qb, q, qt, alpha, g.idz);
+      const double f = gz + (HAS_F ? (double)fz[c] : 0.0);
+      Hv = q + dt * (nu * lap - conv + f);
+    }
+    if (ci <= g.hi[0]) F[c] = T(Fv);
+    if (cj <= g.hi[1]) G[c] = T(Gv);
+    if (ck <= g.hi[2]) H[c] = T(Hv);
+  });
+}
+
 // ---------------------------------------------------------------------------
 // Poisson right-hand side rhs = (div F) / dt on every cell (the face below
 // cell 1 of a periodic axis is face n), with the RMS of rhs reduced into the

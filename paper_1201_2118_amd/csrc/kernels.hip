@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cells.h"
+#include "convection.h"
 #include "ns_internal.h"
 #include "reduce.h"
 
@@ -289,6 +290,18 @@ __global__ void k_mask(double* __restrict__ q, Geo g, int comp) {
   }
 }
 
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_fgh_adv(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
+          const T* __restrict__ fx, const T* __restrict__ fy, const T* __restrict__ fz,
+          T* __restrict__ F, T* __restrict__ G, T* __restrict__ H, Geo g, const Ctl* __restrict__ ctl,
+          double nu, double alpha, double gx, double gy, double gz) {
+  if (fx)
+    fgh_adv_cells<T, true>(g, zr, own_blk(), u, v, w, fx, fy, fz, F, G, H, ctl, nu, alpha, gx, gy, gz);
+  else
+    fgh_adv_cells<T, false>(g, zr, own_blk(), u, v, w, fx, fy, fz, F, G, H, ctl, nu, alpha, gx, gy, gz);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -334,6 +347,21 @@ hipError_t launch_fgh(hipStream_t st, const Geo& g, const T* u, const T* v, cons
                                                      gamma, gf[0], gf[1], gf[2]);
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_fgh_advective(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, const T* fx,
+                                const T* fy, const T* fz, T* F, T* G, T* H, const Ctl* ctl, double re, double alpha,
+                                const double gf[3]) {
+  k_fgh_adv<T><<<cell_grid(g, 0), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, 0), u, v, w, fx, fy, fz, F, G, H, g,
+                                                                  ctl, 1.0 / re, alpha, gf[0], gf[1], gf[2]);
+  return hipGetLastError();
+}
+template hipError_t launch_fgh_advective<double>(hipStream_t, const Geo&, const double*, const double*, const double*,
+                                                 const double*, const double*, const double*, double*, double*,
+                                                 double*, const Ctl*, double, double, const double[3]);
+template hipError_t launch_fgh_advective<float>(hipStream_t, const Geo&, const float*, const float*, const float*,
+                                                const float*, const float*, const float*, float*, float*, float*,
+                                                const Ctl*, double, double, const double[3]);
 
 size_t reduce_blocks(const Geo& g) {
   long n = (long)g.nx * g.ny * g.nz;

@@ -17,6 +17,7 @@
 #include <string>
 #include <vector>
 
+#include "convection.h"
 #include "generated.h"
 #include "ns.h"
 #include "ns_internal.h"
@@ -223,7 +224,12 @@ ns_status validate(const ns_params& p, int idx) {
       if (!std::isfinite(p.wall_vel[f][c])) return bad("wall velocities must be finite");
   for (int c = 0; c < 3; c++)
     if (!std::isfinite(p.g[c])) return bad("body force must be finite");
-  if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING | NS_BATCH_LAUNCHES | NS_GENERATED)) return bad("unknown flag bits");
+  if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING | NS_BATCH_LAUNCHES | NS_GENERATED | NS_ADVECTIVE))
+    return bad("unknown flag bits");
+  if ((p.flags & NS_ADVECTIVE) && (p.flags & NS_GENERATED))
+    return bad("the generated predictor has the conservative form (NS_ADVECTIVE with NS_GENERATED)");
+  if ((p.flags & NS_ADVECTIVE) && p.checkpoint_every > 0)
+    return bad("the adjoint covers the conservative form only (NS_ADVECTIVE with checkpoint_every)");
   if (!(p.tile[0] == -1 || p.tile[0] == 0 || p.tile[0] == 4 || p.tile[0] == 8 || p.tile[0] == 12 ||
         p.tile[0] == 16 || p.tile[0] == 24 || p.tile[0] == 32))
     return bad("tile[0] must be -1, 0, 4, 8, 12, 16, 24 or 32");
@@ -734,7 +740,10 @@ ns_status step_pre(ns_solver* s, int idx, State& S) {
   }
   {
     Timed t(s, NS_T_FGH);
-    if (p.flags & NS_GENERATED)
+    if (p.flags & NS_ADVECTIVE)
+      HCK(s, launch_fgh_advective<T>(s->stream, g, u, v, w, (const T*)I.frc[0], (const T*)I.frc[1],
+                                     (const T*)I.frc[2], (T*)I.F, (T*)I.G, (T*)I.H, I.ctl, p.re, p.gamma, p.g));
+    else if (p.flags & NS_GENERATED)
       HCK(s, launch_gen_fgh<T>(s->stream, g, u, v, w, (const T*)I.frc[0], (const T*)I.frc[1], (const T*)I.frc[2],
                                (T*)I.F, (T*)I.G, (T*)I.H, I.ctl, p.re, p.gamma, p.g));
     else
@@ -1629,8 +1638,8 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
   for (int i = 0; i < n_instances; i++) {
     ns_status st = validate(params[i], i);
     if (st != NS_OK) return st;
-    if ((params[i].flags & NS_GENERATED) && n_instances > 1)
-      return fail(nullptr, NS_E_INVALID, "NS_GENERATED needs a handle of one instance");
+    if ((params[i].flags & (NS_GENERATED | NS_ADVECTIVE)) && n_instances > 1)
+      return fail(nullptr, NS_E_INVALID, "NS_GENERATED and NS_ADVECTIVE need a handle of one instance");
   }
   ns_solver* s = new ns_solver();
   if (hipGetDevice(&s->device) != hipSuccess) {

@@ -42,6 +42,8 @@ def make_params(prm: dict) -> abi.ns_params:
     p.precision = abi.NS_MIXED if prec in ("mixed", abi.NS_MIXED) else abi.NS_FP64
     p.checkpoint_every = int(prm.get("checkpoint_every", 0))
     p.flags = int(prm.get("flags", 0))
+    if prm.get("convection", "conservative") == "advective":
+        p.flags |= abi.NS_ADVECTIVE
     tile = prm.get("tile", (0, 0))
     p.tile[0], p.tile[1] = int(tile[0]), int(tile[1])
     return p

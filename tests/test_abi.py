@@ -134,3 +134,15 @@ def test_noalloc_step_validates_before_any_device_call():
     assert code == abi.NS_E_INVALID
     code = abi.ns_step_noalloc(make_params(W.cavity(8)), 1, 1, 1, 1, -1, None, None)
     assert code == abi.NS_E_INVALID
+
+
+def test_advective_form_refuses_unsupported_combinations():
+    """NS_ADVECTIVE: one instance, not with the generated kernels, not with
+    recording for the adjoint (host-side validation)."""
+    prm = dict(W.cavity(8), convection="advective")
+    assert _create(prm, flags=abi.NS_GENERATED)[0] == abi.NS_E_INVALID
+    assert _create(dict(prm, checkpoint_every=2))[0] == abi.NS_E_INVALID
+    arr = (abi.ns_params * 2)(make_params(prm), make_params(prm))
+    h = ctypes.c_void_p()
+    assert abi.ns_create(arr, 2, None, h) == abi.NS_E_INVALID
+    assert "one instance" in abi.ns_last_error(None)
