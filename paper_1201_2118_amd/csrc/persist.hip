@@ -90,7 +90,7 @@ __device__ __forceinline__ bool team_sync(Team& t, int* sh_flag) {
   t.gen += 1;
   if (flat_tid() == 0) {
     int ok = 1;
-    __threadfence();  // release this workgroup's writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this workgroup's writes before its arrival
     atomicAdd(t.bar, 1u);
     const unsigned target = t.gen * (unsigned)t.size;
     const long long t0 = wall_clock64();
@@ -106,7 +106,7 @@ __device__ __forceinline__ bool team_sync(Team& t, int* sh_flag) {
       }
       __builtin_amdgcn_s_sleep(2);
     }
-    __threadfence();  // acquire the team's writes
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the team's writes after the wait
     *sh_flag = ok;
   }
   __syncthreads();
