@@ -301,6 +301,7 @@ struct PItem {
   double re, tau, gamma, omega, tol, eta;
   int adaptive;        // dt from the velocity every step
   int itermax;
+  int ns_max;          // sweeps per pass (1 or 2)
   int team;            // workgroups of the domain's team
   int cgx, cgy, cgz;   // cell-stage blocks per axis
 };

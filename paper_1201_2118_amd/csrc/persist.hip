@@ -342,6 +342,7 @@ __device__ __forceinline__ void persist_body(const PItem* __restrict__ items, co
   const long n = (long)g.nx * g.ny * g.nz;
   const int nvb = uni(it.cgx * it.cgy * it.cgz);
   const int itermax = uni(it.itermax);
+  const int ns_max = uni(it.ns_max);
   const int adaptive = uni(it.adaptive);
   const bool has_f = uni(it.frc[0] != nullptr);
   for (int q = flat_tid(); q < 2 * 2 * 2 * kEdge<kPW>; q += kPThreads) E[q] = T(0);
@@ -430,7 +431,7 @@ __device__ __forceinline__ void persist_body(const PItem* __restrict__ items, co
         const int budget = itermax - used;
         int m = 0, cur = 0, f = 0, fb = 0;
         for (;;) {
-          const int ns = m + 2 <= budget ? 2 : 1;
+          const int ns = ns_max == 2 && m + 2 <= budget ? 2 : 1;
           double a1 = 0.0, a2 = 0.0;
           team_pass_any<float>(it, g, t, ns, m == 0, e[cur], e[cur ^ 1], r, 1, (float*)E, a1, a2);
           const double s1 = block_sum(a1, S.sh);
@@ -507,7 +508,7 @@ __device__ __forceinline__ void persist_body(const PItem* __restrict__ items, co
       int m = 0, cur = pc, f = 0, fb = pc;
       if (!uni(S.lc.done)) {
         for (;;) {
-          const int ns = m < itermax ? (m + 2 <= itermax ? 2 : 1) : 0;
+          const int ns = m < itermax ? (ns_max == 2 && m + 2 <= itermax ? 2 : 1) : 0;
           double a1 = 0.0, a2 = 0.0;
           if (ns > 0) team_pass_any<double>(it, g, t, ns, false, P[cur], P[cur ^ 1], rd, 1, (double*)E, a1, a2);
           else team_pass_any<double>(it, g, t, 1, false, P[cur], P[cur ^ 1], rd, 0, (double*)E, a1, a2);

@@ -1270,21 +1270,51 @@ ns_status step_batched(ns_solver* s) {
 }
 
 // ---- persistent batched launch ---------------------------------------------------
+// Plane-steps the busiest workgroup of a team of `team` spends on one pass
+// over a domain (16-row two-sweep tiles, each workgroup an equal share of
+// the (plane-column, plane) space cut at column ends, as the kernel splits
+// it): a z range of planes z0..z1 costs z1 - z0 + 7 steps (the pipeline
+// runs 2 planes before and 4 after it).  A step's time is about the same
+// for every tile, so this is the team's time per pass.
+long pass_steps(const Geo& g, int team) {
+  const int ntx = (g.nx + 55) / 56, nty = (g.ny + 7) / 8;
+  const long ptot = (long)ntx * nty * g.nz;
+  long worst = 0;
+  for (int r = 0; r < team; r++) {
+    long q0 = ptot * r / team, st = 0;
+    const long q1 = ptot * (r + 1) / team;
+    while (q0 < q1) {
+      const long col = q0 / g.nz;
+      const long z0 = q0 - col * g.nz + 1;
+      const long z1 = std::min((long)g.nz, z0 + (q1 - q0) - 1);
+      st += z1 - z0 + 7;
+      q0 += z1 - z0 + 1;
+    }
+    worst = std::max(worst, st);
+  }
+  return worst;
+}
+
 // Teams: the co-resident workgroups of the launch are split among the
 // domains.  Workgroup b runs on XCD b mod 8; the domains are dealt to the
-// XCDs longest-processing-time first (by cell count), and the workgroups of
-// an XCD are shared among its domains in proportion to their cell counts
-// (at least one each), so a domain's team sits on one XCD (one L2).
-// Returns false when some XCD would get more domains than workgroups.
-bool persist_teams(const std::vector<long long>& cells, int G, std::vector<PSlot>& slots, std::vector<int>& team) {
-  const int n = (int)cells.size();
+// XCDs longest-processing-time first by their pass work (tile columns x
+// planes), and the workgroups of an XCD are handed out one at a time to the
+// domain whose team currently has the longest pass (pass_steps), so a
+// domain's team sits on one XCD (one L2) and the teams finish a pass at
+// about the same time.  Returns false when some XCD would get more domains
+// than workgroups.
+bool persist_teams(const std::vector<Geo>& geo, int G, std::vector<PSlot>& slots, std::vector<int>& team) {
+  const int n = (int)geo.size();
   slots.assign(G, PSlot{-1, 0});
   team.assign(n, 0);
   int gx[8];
   for (int x = 0; x < 8; x++) gx[x] = G / 8 + (x < G % 8 ? 1 : 0);
+  std::vector<long long> work(n);
+  for (int d = 0; d < n; d++)
+    work[d] = (long long)((geo[d].nx + 55) / 56) * ((geo[d].ny + 7) / 8) * geo[d].nz;
   std::vector<int> ord(n);
   for (int i = 0; i < n; i++) ord[i] = i;
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cells[a] > cells[b]; });
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work[a] > work[b]; });
   long long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<int> on[8];
   for (int d : ord) {
@@ -1293,34 +1323,22 @@ bool persist_teams(const std::vector<long long>& cells, int G, std::vector<PSlot
       if ((int)on[x].size() < gx[x] && (best < 0 || load[x] < load[best])) best = x;
     if (best < 0) return false;
     on[best].push_back(d);
-    load[best] += cells[d];
+    load[best] += work[d];
   }
   for (int x = 0; x < 8; x++) {
     if (on[x].empty()) continue;
-    long long cx = 0;
-    for (int d : on[x]) cx += cells[d];
-    int sum = 0;
-    for (int d : on[x]) {
-      team[d] = std::max(1, (int)((double)gx[x] * (double)cells[d] / (double)cx));
-      sum += team[d];
+    std::vector<long> cost(on[x].size());
+    for (size_t q = 0; q < on[x].size(); q++) {
+      team[on[x][q]] = 1;
+      cost[q] = pass_steps(geo[on[x][q]], 1);
     }
-    // hand out the rest to the domains with the most cells per workgroup,
-    // take back from those with the fewest
-    while (sum < gx[x]) {
-      int best = on[x][0];
-      for (int d : on[x])
-        if ((double)cells[d] / team[d] > (double)cells[best] / team[best]) best = d;
-      team[best]++;
-      sum++;
-    }
-    while (sum > gx[x]) {
-      int best = -1;
-      for (int d : on[x])
-        if (team[d] > 1 && (best < 0 || (double)cells[d] / (team[d] - 1) < (double)cells[best] / (team[best] - 1)))
-          best = d;
-      if (best < 0) return false;
-      team[best]--;
-      sum--;
+    for (int k = (int)on[x].size(); k < gx[x]; k++) {
+      size_t q = 0;
+      for (size_t c = 1; c < cost.size(); c++)
+        if (cost[c] > cost[q]) q = c;
+      const int d = on[x][q];
+      team[d]++;
+      cost[q] = pass_steps(geo[d], team[d]);
     }
     int slot = 0;
     for (int d : on[x])
@@ -1328,6 +1346,13 @@ bool persist_teams(const std::vector<long long>& cells, int G, std::vector<PSlot
   }
   return true;
 }
+
+// Sweeps per pass of a domain in the persistent launch: two (the pass
+// tile's temporal blocking).  One-sweep tiles recompute less halo (60 of 64
+// lanes, 12 of 16 rows against 56 and 8) but need twice the passes and
+// team barriers; on the 64-cavity workload they measured slower (699
+// against 748 Mcell-steps/s), as did a per-domain choice by tile cost.
+int persist_sweeps_per_pass(const Geo&) { return 2; }
 
 // Sets up the persistent launch of a batched handle; leaves s->persist
 // false (and allocates nothing) when the handle does not qualify.
@@ -1342,11 +1367,11 @@ ns_status persist_setup(ns_solver* s) {
     return NS_OK;
   const int G = persistent_resident(f32);
   if (G < n) return NS_OK;
-  std::vector<long long> cells(n);
-  for (int i = 0; i < n; i++) cells[i] = (long long)s->in[i].g.nx * s->in[i].g.ny * s->in[i].g.nz;
+  std::vector<Geo> geo(n);
+  for (int i = 0; i < n; i++) geo[i] = s->in[i].g;
   std::vector<PSlot> slots;
   std::vector<int> team;
-  if (!persist_teams(cells, G, slots, team)) return NS_OK;
+  if (!persist_teams(geo, G, slots, team)) return NS_OK;
   int rate = 0;
   HCK(s, hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, s->device));
   s->clock_khz = rate > 0 ? (double)rate : 100000.0;
@@ -1426,6 +1451,7 @@ ns_status persist_run(ns_solver* s, int nsteps) {
     it.eta = I.prm.eta;
     it.adaptive = I.prm.dt <= 0;
     it.itermax = I.prm.itermax;
+    it.ns_max = persist_sweeps_per_pass(I.g);
     it.cgx = (I.g.nx + kCellX - 1) / kCellX;
     it.cgy = (I.g.ny + kPersistWaves - 1) / kPersistWaves;
     it.cgz = (I.g.nz + kPersistZr - 1) / kPersistZr;
