@@ -261,10 +261,15 @@ template <class T> hipError_t launch_stage_batched(hipStream_t st, int kind, con
 hipError_t launch_defect_batched(hipStream_t st, const StageItem* d_items, int nitems, int nblocks);
 
 // ---- persistent batched launch (persist.hip) ----
-// Workgroups of 64 x kPersistWaves threads; cell-stage blocks of 64 x
-// kPersistWaves cells and kPersistZr planes; two-sweep pass tiles of 16
-// rows.
-constexpr int kPersistWaves = 8;
+// Workgroups of 64 x W threads (W waves: 16 for FP32 storage, 8 for FP64,
+// one workgroup per compute unit); cell-stage blocks of 64 x W cells and
+// kPersistZr planes; two-sweep pass tiles of R rows per lane, R x W rows.
+constexpr int kPersistWaves32 = 16, kPersistWaves64 = 8;
+constexpr int kPersistRpl32 = 2, kPersistRpl64 = 2;
+inline int persist_waves(bool f32) { return f32 ? kPersistWaves32 : kPersistWaves64; }
+inline int persist_rows(bool f32) {
+  return f32 ? kPersistRpl32 * kPersistWaves32 : kPersistRpl64 * kPersistWaves64;
+}
 constexpr int kPersistZr = 4;
 // Statistics of one domain, kept on the device across the launch (the
 // host's ns_stats plus the pressure buffer in use and the sweep time).

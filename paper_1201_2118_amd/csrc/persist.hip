@@ -2,8 +2,8 @@
 // cooperative launch.
 //
 // The workgroups of the launch (as many as are co-resident) are split into
-// teams, one per domain, sized by the domain's cell count and placed on one
-// XCD each (workgroup b runs on XCD b mod 8).  A team runs its domain's
+// teams, one per domain, sized by the length of the domain's pass and placed on
+// one XCD each (workgroup b runs on XCD b mod 8).  A team runs its domain's
 // steps on its own: every stage (time step, boundary fill, predictor, rhs,
 // the Poisson solve, pressure ghosts, projection) is spread over the team's
 // workgroups, and a team barrier (a counter in device memory, device-scope
@@ -34,10 +34,14 @@ namespace ns {
 
 namespace {
 
-constexpr int kPW = kPersistWaves;   // waves per workgroup (rows of a cell-stage block)
-constexpr int kPR = 2;               // rows per lane of the 16-row pass tile
-constexpr int kPThreads = 64 * kPW;
-static_assert(kPR * kPW == 16, "16-row pass tiles");
+template <class T>
+constexpr int waves_of() {
+  return sizeof(T) == 4 ? kPersistWaves32 : kPersistWaves64;
+}
+template <class T>
+constexpr int rpl_of() {  // rows per lane of the pass tile
+  return sizeof(T) == 4 ? kPersistRpl32 : kPersistRpl64;
+}
 
 // A value every lane of the wave holds alike (read from LDS after a
 // barrier), made visibly uniform so that what depends on it (buffer
@@ -113,7 +117,8 @@ __device__ __forceinline__ bool team_sync(Team& t, int* sh_flag) {
   return uni(*sh_flag) != 0;
 }
 
-// Cell-stage block vb of a domain (64 x kPW cells, kPersistZr planes).
+// Cell-stage block vb of a domain (64 lanes x one row per wave, kPersistZr
+// planes).
 __device__ __forceinline__ CellBlk vblock(const PItem& it, int vb) {
   CellBlk b;
   b.x = vb % it.cgx;
@@ -128,7 +133,8 @@ __device__ __forceinline__ CellBlk vblock(const PItem& it, int vb) {
 // team's threads.
 template <class F>
 __device__ __forceinline__ void team_loop(const Team& t, long n, F&& f) {
-  for (long e = (long)t.rank * kPThreads + flat_tid(); e < n; e += (long)t.size * kPThreads) f(e);
+  const int nt = (int)(blockDim.x * blockDim.y);
+  for (long e = (long)t.rank * nt + flat_tid(); e < n; e += (long)t.size * nt) f(e);
 }
 
 // Periodic images of entry (a, b) of the face of axis ax (full extent of
@@ -281,8 +287,9 @@ template <class T, int NS, bool ZIN>
 __device__ __forceinline__ void team_pass(const PItem& it, const Geo& g, const Team& t, const T* pin, T* pout, const T* rhs, int write,
                           T* E, double& acc1, double& acc2) {
   constexpr int H = 2 * NS;
+  constexpr int W = waves_of<T>(), R = rpl_of<T>();
   const int ntx = (g.nx + (64 - 2 * H) - 1) / (64 - 2 * H);
-  const int nty = (g.ny + (16 - 2 * H) - 1) / (16 - 2 * H);
+  const int nty = (g.ny + (R * W - 2 * H) - 1) / (R * W - 2 * H);
   const long ptot = (long)ntx * nty * g.nz;
   long q0 = ptot * t.rank / t.size;
   const long q1 = ptot * (t.rank + 1) / t.size;
@@ -290,7 +297,7 @@ __device__ __forceinline__ void team_pass(const PItem& it, const Geo& g, const T
     const int col = (int)(q0 / g.nz);
     const int z0 = (int)(q0 - (long)col * g.nz) + 1;
     const int z1 = (int)min((long)g.nz, (long)z0 + (q1 - q0) - 1);
-    pass_tile<T, NS, kPR, kPW, ZIN, true>(uni_ptr(pin), uni_ptr(pout), uni_ptr(rhs), g, it.omega, write, col, z0, z1,
+    pass_tile<T, NS, R, W, ZIN, true>(uni_ptr(pin), uni_ptr(pout), uni_ptr(rhs), g, it.omega, write, col, z0, z1,
                                           ntx, E, acc1, acc2);
     __syncthreads();
     q0 += z1 - z0 + 1;
@@ -345,7 +352,7 @@ __device__ __forceinline__ void persist_body(const PItem* __restrict__ items, co
   const int ns_max = uni(it.ns_max);
   const int adaptive = uni(it.adaptive);
   const bool has_f = uni(it.frc[0] != nullptr);
-  for (int q = flat_tid(); q < 2 * 2 * 2 * kEdge<kPW>; q += kPThreads) E[q] = T(0);
+  for (int q = flat_tid(); q < 2 * 2 * 2 * kEdge<waves_of<T>()>; q += 64 * waves_of<T>()) E[q] = T(0);
   if (flat_tid() == 0) S.lc = *it.ctl;
   int pc = uni(it.st->pcur);
   __syncthreads();
@@ -590,19 +597,19 @@ __device__ __forceinline__ void persist_body(const PItem* __restrict__ items, co
   }
 }
 
-// FP32: two workgroups per compute unit (four waves per SIMD, 128
-// registers); FP64: one.
-__global__ void __launch_bounds__(kPThreads, 4)
+// One workgroup per compute unit: FP32 16 waves (four per SIMD, 128
+// registers), FP64 8 waves (two per SIMD).
+__global__ void __launch_bounds__(64 * kPersistWaves32, kPersistWaves32 / 4)
 k_persist_f32(const PItem* __restrict__ items, const PSlot* __restrict__ slots, int nsteps, int* err,
               long long limit) {
-  __shared__ float E[2 * 2 * 2 * kEdge<kPW>];
+  __shared__ float E[2 * 2 * 2 * kEdge<kPersistWaves32>];
   __shared__ Shared S;
   persist_body<float>(items, slots, nsteps, err, limit, E, S);
 }
-__global__ void __launch_bounds__(kPThreads, 2)
+__global__ void __launch_bounds__(64 * kPersistWaves64, kPersistWaves64 / 4)
 k_persist_f64(const PItem* __restrict__ items, const PSlot* __restrict__ slots, int nsteps, int* err,
               long long limit) {
-  __shared__ double E[2 * 2 * 2 * kEdge<kPW>];
+  __shared__ double E[2 * 2 * 2 * kEdge<kPersistWaves64>];
   __shared__ Shared S;
   persist_body<double>(items, slots, nsteps, err, limit, E, S);
 }
@@ -614,7 +621,7 @@ int resident_of() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sizeof(T) == 4 ? (const void*)k_persist_f32 : (const void*)k_persist_f64, kPThreads, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sizeof(T) == 4 ? (const void*)k_persist_f32 : (const void*)k_persist_f64, 64 * waves_of<T>(), 0) != hipSuccess)
     return 0;
   cached = cus * per_cu;
   return cached;
@@ -627,7 +634,7 @@ int persistent_resident(bool f32) { return f32 ? resident_of<float>() : resident
 hipError_t launch_persistent(hipStream_t st, bool f32, const PItem* items, const PSlot* slots, int nblocks,
                              int nsteps, int* err, long long limit) {
   void* args[] = {(void*)&items, (void*)&slots, (void*)&nsteps, (void*)&err, (void*)&limit};
-  const dim3 grid(nblocks), blk(64, kPW);  // 64 lanes in x, one wave per row group in y
+  const dim3 grid(nblocks), blk(64, persist_waves(f32));  // 64 lanes in x, one wave per row group in y
   if (f32) return hipLaunchCooperativeKernel((const void*)k_persist_f32, grid, blk, args, 0, st);
   return hipLaunchCooperativeKernel((const void*)k_persist_f64, grid, blk, args, 0, st);
 }

@@ -1271,13 +1271,13 @@ ns_status step_batched(ns_solver* s) {
 
 // ---- persistent batched launch ---------------------------------------------------
 // Plane-steps the busiest workgroup of a team of `team` spends on one pass
-// over a domain (16-row two-sweep tiles, each workgroup an equal share of
-// the (plane-column, plane) space cut at column ends, as the kernel splits
-// it): a z range of planes z0..z1 costs z1 - z0 + 7 steps (the pipeline
-// runs 2 planes before and 4 after it).  A step's time is about the same
-// for every tile, so this is the team's time per pass.
-long pass_steps(const Geo& g, int team) {
-  const int ntx = (g.nx + 55) / 56, nty = (g.ny + 7) / 8;
+// over a domain (two-sweep tiles of `rows` rows, each workgroup an equal
+// share of the (plane-column, plane) space cut at column ends, as the
+// kernel splits it): a z range of planes z0..z1 costs z1 - z0 + 7 steps
+// (the pipeline runs 2 planes before and 4 after it).  A step's time is
+// about the same for every tile, so this is the team's time per pass.
+long pass_steps(const Geo& g, int team, int rows) {
+  const int ntx = (g.nx + 55) / 56, nty = (g.ny + rows - 9) / (rows - 8);
   const long ptot = (long)ntx * nty * g.nz;
   long worst = 0;
   for (int r = 0; r < team; r++) {
@@ -1303,7 +1303,8 @@ long pass_steps(const Geo& g, int team) {
 // domain's team sits on one XCD (one L2) and the teams finish a pass at
 // about the same time.  Returns false when some XCD would get more domains
 // than workgroups.
-bool persist_teams(const std::vector<Geo>& geo, int G, std::vector<PSlot>& slots, std::vector<int>& team) {
+bool persist_teams(const std::vector<Geo>& geo, int G, int rows, std::vector<PSlot>& slots,
+                   std::vector<int>& team) {
   const int n = (int)geo.size();
   slots.assign(G, PSlot{-1, 0});
   team.assign(n, 0);
@@ -1311,7 +1312,7 @@ bool persist_teams(const std::vector<Geo>& geo, int G, std::vector<PSlot>& slots
   for (int x = 0; x < 8; x++) gx[x] = G / 8 + (x < G % 8 ? 1 : 0);
   std::vector<long long> work(n);
   for (int d = 0; d < n; d++)
-    work[d] = (long long)((geo[d].nx + 55) / 56) * ((geo[d].ny + 7) / 8) * geo[d].nz;
+    work[d] = (long long)((geo[d].nx + 55) / 56) * ((geo[d].ny + rows - 9) / (rows - 8)) * geo[d].nz;
   std::vector<int> ord(n);
   for (int i = 0; i < n; i++) ord[i] = i;
   std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work[a] > work[b]; });
@@ -1330,7 +1331,7 @@ bool persist_teams(const std::vector<Geo>& geo, int G, std::vector<PSlot>& slots
     std::vector<long> cost(on[x].size());
     for (size_t q = 0; q < on[x].size(); q++) {
       team[on[x][q]] = 1;
-      cost[q] = pass_steps(geo[on[x][q]], 1);
+      cost[q] = pass_steps(geo[on[x][q]], 1, rows);
     }
     for (int k = (int)on[x].size(); k < gx[x]; k++) {
       size_t q = 0;
@@ -1338,7 +1339,7 @@ bool persist_teams(const std::vector<Geo>& geo, int G, std::vector<PSlot>& slots
         if (cost[c] > cost[q]) q = c;
       const int d = on[x][q];
       team[d]++;
-      cost[q] = pass_steps(geo[d], team[d]);
+      cost[q] = pass_steps(geo[d], team[d], rows);
     }
     int slot = 0;
     for (int d : on[x])
@@ -1371,7 +1372,7 @@ ns_status persist_setup(ns_solver* s) {
   for (int i = 0; i < n; i++) geo[i] = s->in[i].g;
   std::vector<PSlot> slots;
   std::vector<int> team;
-  if (!persist_teams(geo, G, slots, team)) return NS_OK;
+  if (!persist_teams(geo, G, persist_rows(f32), slots, team)) return NS_OK;
   int rate = 0;
   HCK(s, hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, s->device));
   s->clock_khz = rate > 0 ? (double)rate : 100000.0;
@@ -1453,7 +1454,7 @@ ns_status persist_run(ns_solver* s, int nsteps) {
     it.itermax = I.prm.itermax;
     it.ns_max = persist_sweeps_per_pass(I.g);
     it.cgx = (I.g.nx + kCellX - 1) / kCellX;
-    it.cgy = (I.g.ny + kPersistWaves - 1) / kPersistWaves;
+    it.cgy = (I.g.ny + persist_waves(f32) - 1) / persist_waves(f32);
     it.cgz = (I.g.nz + kPersistZr - 1) / kPersistZr;
     PStats& ps = s->pstats_h[i];
     ps = PStats{};
