@@ -17,6 +17,8 @@
 #include <string>
 #include <vector>
 
+#include <sys/stat.h>
+
 #include "convection.h"
 #include "generated.h"
 #include "ns.h"
@@ -279,8 +281,14 @@ hipError_t dmalloc(void** p, size_t bytes);
 // 4 / 8 / 12, each with the whole column, z chunks 32 / 64 / 128, and the z
 // chunks that make the tile count just fit k times the resident workgroups
 // (k = 1..8), which avoids a nearly empty last round of tiles.  Results are
-// cached per grid shape, storage precision and boundary kind for the life
-// of the process.
+// cached per grid shape, storage precision and boundary kind: in the process,
+// and in a text file shared by processes (one line per result, keyed also by
+// the device's architecture name, its compute-unit count and the library
+// build, so a rebuilt library or another GPU tunes afresh).  The file is
+// $NS_TUNE_CACHE, else $XDG_CACHE_HOME/nsmi/tune.txt, else
+// $HOME/.cache/nsmi/tune.txt; NS_TUNE_CACHE=off (or empty) keeps results in
+// the process only.  A line that does not parse or names a shape the
+// library would not run is ignored.
 struct TuneKey {
   int nx, ny, nz, esz, per;
   bool operator==(const TuneKey& o) const {
@@ -289,6 +297,77 @@ struct TuneKey {
 };
 std::mutex g_tune_mu;
 std::vector<std::pair<TuneKey, SorShape>> g_tune_cache;
+bool g_tune_loaded = false;
+constexpr const char* kTuneBuild = "v1-" __DATE__ "-" __TIME__;
+
+std::string tune_file() {
+  const char* e = getenv("NS_TUNE_CACHE");
+  if (e) return (e[0] == 0 || strcmp(e, "off") == 0) ? std::string() : std::string(e);
+  if (const char* x = getenv("XDG_CACHE_HOME"); x && x[0]) return std::string(x) + "/nsmi/tune.txt";
+  if (const char* h = getenv("HOME"); h && h[0]) return std::string(h) + "/.cache/nsmi/tune.txt";
+  return std::string();
+}
+
+// "<arch> <compute units> <build>" of the current device, spaces in the
+// build stamp replaced.
+std::string tune_device_tag(int device) {
+  hipDeviceProp_t pr;
+  if (hipGetDeviceProperties(&pr, device) != hipSuccess) return std::string();
+  std::string b = kTuneBuild;
+  for (char& c : b)
+    if (c == ' ') c = '_';
+  char buf[512];
+  snprintf(buf, sizeof buf, "%s %d %s", pr.gcnArchName, pr.multiProcessorCount, b.c_str());
+  for (char* q = buf; *q; q++)
+    if (*q == '\n') *q = ' ';
+  return std::string(buf);
+}
+
+bool tune_shape_valid(const SorShape& sh, int esz) {
+  if (sh.ty == 4 || sh.ty == 8 || sh.ty == 12) return sh.zc >= 0;
+  if (sh.ty == 16 || sh.ty == 24 || sh.ty == 32) return sh.zc >= 0 && pass_rows_ok(sh.ty, esz == 4);
+  return false;
+}
+
+// Reads the file's lines for this device into the process cache (caller
+// holds g_tune_mu).
+void tune_load(const std::string& tag) {
+  const std::string path = tune_file();
+  if (path.empty() || tag.empty()) return;
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[1024];
+  while (fgets(line, sizeof line, f)) {
+    char arch[256], build[256];
+    int cus, nx, ny, nz, esz, per, ty, zc;
+    if (sscanf(line, "%255s %d %255s %d %d %d %d %d %d %d", arch, &cus, build, &nx, &ny, &nz, &esz, &per, &ty,
+               &zc) != 10)
+      continue;
+    char mine[512];
+    snprintf(mine, sizeof mine, "%s %d %s", arch, cus, build);
+    if (tag != mine) continue;
+    const TuneKey k{nx, ny, nz, esz, per};
+    const SorShape sh{ty, zc};
+    if (!tune_shape_valid(sh, esz)) continue;
+    bool have = false;
+    for (auto& kv : g_tune_cache) have |= kv.first == k;
+    if (!have) g_tune_cache.push_back({k, sh});
+  }
+  fclose(f);
+}
+
+// Appends one result to the file (creating its directory); failures leave
+// the process cache as the only record.
+void tune_store(const std::string& tag, const TuneKey& k, const SorShape& sh) {
+  const std::string path = tune_file();
+  if (path.empty() || tag.empty()) return;
+  for (size_t q = 1; q < path.size(); q++)
+    if (path[q] == '/') (void)mkdir(path.substr(0, q).c_str(), 0755);
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d %d %d %d %d %d\n", tag.c_str(), k.nx, k.ny, k.nz, k.esz, k.per, sh.ty, sh.zc);
+  fclose(f);
+}
 
 template <class T>
 ns_status tune_run(ns_solver* s, Inst& I, Ctl* tctl, const SorShape& sh, float* ms) {
@@ -324,8 +403,13 @@ ns_status autotune(ns_solver* s, Inst& I) {
   const long n = (long)I.g.nx * I.g.ny * I.g.nz;
   if (I.prm.tile[0] != 0 || n < (1L << 21)) return NS_OK;
   const TuneKey key{I.g.nx, I.g.ny, I.g.nz, (int)I.esz, I.g.per[0] | (I.g.per[1] << 1) | (I.g.per[2] << 2)};
+  const std::string tag = tune_device_tag(s->device);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) {
+      tune_load(tag);
+      g_tune_loaded = true;
+    }
     for (auto& kv : g_tune_cache)
       if (kv.first == key) { I.shape = kv.second; return NS_OK; }
   }
@@ -363,6 +447,7 @@ ns_status autotune(ns_solver* s, Inst& I) {
   I.shape = pick;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache.push_back({key, pick});
+  tune_store(tag, key, pick);
   return NS_OK;
 }
 
