@@ -28,9 +28,65 @@ __device__ __forceinline__ double flux(double t, double a, double b, double gamm
   return 0.5 * (t * (a + b) + gamma * fabs(t) * (a - b));
 }
 
-// HAS_F: body-force fields fx, fy, fz are present (all three or none).  A
-// compile-time choice, so the loop body carries no per-cell branch and the
-// loads of the three components can be in flight together.
+// The predictor's value of each component at cell c (u, v, w with a
+// one-cell neighbourhood of c inside the padded arrays), in FP64.  HAS_F:
+// body-force fields fx, fy, fz are present (all three or none), a
+// compile-time choice so the loop body carries no per-cell branch.
+template <class T, bool HAS_F>
+__device__ __forceinline__ double F_at(const Geo& g, long c, const T* __restrict__ u, const T* __restrict__ v,
+                                       const T* __restrict__ w, const T* __restrict__ fx, double dt, double nu,
+                                       double gamma, double gx) {
+  const long sx = g.sx, sxy = g.sxy;
+  const double q = u[c], qe = u[c + 1], qw = u[c - 1], qn = u[c + sx], qs = u[c - sx], qt = u[c + sxy],
+               qb = u[c - sxy];
+  const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 + (qt - 2.0 * q + qb) * g.idz2;
+  const double cx = (flux(0.5 * (q + qe), q, qe, gamma) - flux(0.5 * (qw + q), qw, q, gamma)) * g.idx;
+  const double vn = 0.5 * ((double)v[c] + (double)v[c + 1]);
+  const double vs = 0.5 * ((double)v[c - sx] + (double)v[c - sx + 1]);
+  const double cy = (flux(vn, q, qn, gamma) - flux(vs, qs, q, gamma)) * g.idy;
+  const double wt = 0.5 * ((double)w[c] + (double)w[c + 1]);
+  const double wb = 0.5 * ((double)w[c - sxy] + (double)w[c - sxy + 1]);
+  const double cz = (flux(wt, q, qt, gamma) - flux(wb, qb, q, gamma)) * g.idz;
+  const double f = gx + (HAS_F ? (double)fx[c] : 0.0);
+  return q + dt * (nu * lap - cx - cy - cz + f);
+}
+template <class T, bool HAS_F>
+__device__ __forceinline__ double G_at(const Geo& g, long c, const T* __restrict__ u, const T* __restrict__ v,
+                                       const T* __restrict__ w, const T* __restrict__ fy, double dt, double nu,
+                                       double gamma, double gy) {
+  const long sx = g.sx, sxy = g.sxy;
+  const double q = v[c], qe = v[c + 1], qw = v[c - 1], qn = v[c + sx], qs = v[c - sx], qt = v[c + sxy],
+               qb = v[c - sxy];
+  const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 + (qt - 2.0 * q + qb) * g.idz2;
+  const double ue = 0.5 * ((double)u[c] + (double)u[c + sx]);
+  const double uw = 0.5 * ((double)u[c - 1] + (double)u[c - 1 + sx]);
+  const double cx = (flux(ue, q, qe, gamma) - flux(uw, qw, q, gamma)) * g.idx;
+  const double cy = (flux(0.5 * (q + qn), q, qn, gamma) - flux(0.5 * (qs + q), qs, q, gamma)) * g.idy;
+  const double wt = 0.5 * ((double)w[c] + (double)w[c + sx]);
+  const double wb = 0.5 * ((double)w[c - sxy] + (double)w[c - sxy + sx]);
+  const double cz = (flux(wt, q, qt, gamma) - flux(wb, qb, q, gamma)) * g.idz;
+  const double f = gy + (HAS_F ? (double)fy[c] : 0.0);
+  return q + dt * (nu * lap - cx - cy - cz + f);
+}
+template <class T, bool HAS_F>
+__device__ __forceinline__ double H_at(const Geo& g, long c, const T* __restrict__ u, const T* __restrict__ v,
+                                       const T* __restrict__ w, const T* __restrict__ fz, double dt, double nu,
+                                       double gamma, double gz) {
+  const long sx = g.sx, sxy = g.sxy;
+  const double q = w[c], qe = w[c + 1], qw = w[c - 1], qn = w[c + sx], qs = w[c - sx], qt = w[c + sxy],
+               qb = w[c - sxy];
+  const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 + (qt - 2.0 * q + qb) * g.idz2;
+  const double ue = 0.5 * ((double)u[c] + (double)u[c + sxy]);
+  const double uw = 0.5 * ((double)u[c - 1] + (double)u[c - 1 + sxy]);
+  const double cx = (flux(ue, q, qe, gamma) - flux(uw, qw, q, gamma)) * g.idx;
+  const double vn = 0.5 * ((double)v[c] + (double)v[c + sxy]);
+  const double vs = 0.5 * ((double)v[c - sx] + (double)v[c - sx + sxy]);
+  const double cy = (flux(vn, q, qn, gamma) - flux(vs, qs, q, gamma)) * g.idy;
+  const double cz = (flux(0.5 * (q + qt), q, qt, gamma) - flux(0.5 * (qb + q), qb, q, gamma)) * g.idz;
+  const double f = gz + (HAS_F ? (double)fz[c] : 0.0);
+  return q + dt * (nu * lap - cx - cy - cz + f);
+}
+
 template <class T, bool HAS_F>
 __device__ __forceinline__ void fgh_cells(const Geo& g, int zr, const CellBlk& blk, const T* __restrict__ u,
                                           const T* __restrict__ v, const T* __restrict__ w,
@@ -39,57 +95,13 @@ __device__ __forceinline__ void fgh_cells(const Geo& g, int zr, const CellBlk& b
                                           T* __restrict__ H, const Ctl* __restrict__ ctl, double nu, double gamma,
                                           double gx, double gy, double gz) {
   const double dt = ctl->dt;
-  const long sx = g.sx, sxy = g.sxy;
   // All three components are formed at every cell (their stencils stay
   // inside the padded arrays) and stored where they are unknowns: the body
   // is one straight block, so the loads of all three are in flight together.
   for_cells<2>(g, zr, blk, [&](int ci, int cj, int ck, long c) {
-    double Fv, Gv, Hv;
-    {  // F on the x face i
-      const double q = u[c], qe = u[c + 1], qw = u[c - 1], qn = u[c + sx], qs = u[c - sx],
-                   qt = u[c + sxy], qb = u[c - sxy];
-      const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
-                         (qt - 2.0 * q + qb) * g.idz2;
-      const double cx = (flux(0.5 * (q + qe), q, qe, gamma) - flux(0.5 * (qw + q), qw, q, gamma)) * g.idx;
-      const double vn = 0.5 * ((double)v[c] + (double)v[c + 1]);
-      const double vs = 0.5 * ((double)v[c - sx] + (double)v[c - sx + 1]);
-      const double cy = (flux(vn, q, qn, gamma) - flux(vs, qs, q, gamma)) * g.idy;
-      const double wt = 0.5 * ((double)w[c] + (double)w[c + 1]);
-      const double wb = 0.5 * ((double)w[c - sxy] + (double)w[c - sxy + 1]);
-      const double cz = (flux(wt, q, qt, gamma) - flux(wb, qb, q, gamma)) * g.idz;
-      const double f = gx + (HAS_F ? (double)fx[c] : 0.0);
-      Fv = q + dt * (nu * lap - cx - cy - cz + f);
-    }
-    {  // G on the y face j
-      const double q = v[c], qe = v[c + 1], qw = v[c - 1], qn = v[c + sx], qs = v[c - sx],
-                   qt = v[c + sxy], qb = v[c - sxy];
-      const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
-                         (qt - 2.0 * q + qb) * g.idz2;
-      const double ue = 0.5 * ((double)u[c] + (double)u[c + sx]);
-      const double uw = 0.5 * ((double)u[c - 1] + (double)u[c - 1 + sx]);
-      const double cx = (flux(ue, q, qe, gamma) - flux(uw, qw, q, gamma)) * g.idx;
-      const double cy = (flux(0.5 * (q + qn), q, qn, gamma) - flux(0.5 * (qs + q), qs, q, gamma)) * g.idy;
-      const double wt = 0.5 * ((double)w[c] + (double)w[c + sx]);
-      const double wb = 0.5 * ((double)w[c - sxy] + (double)w[c - sxy + sx]);
-      const double cz = (flux(wt, q, qt, gamma) - flux(wb, qb, q, gamma)) * g.idz;
-      const double f = gy + (HAS_F ? (double)fy[c] : 0.0);
-      Gv = q + dt * (nu * lap - cx - cy - cz + f);
-    }
-    {  // H on the z face k
-      const double q = w[c], qe = w[c + 1], qw = w[c - 1], qn = w[c + sx], qs = w[c - sx],
-                   qt = w[c + sxy], qb = w[c - sxy];
-      const double lap = (qe - 2.0 * q + qw) * g.idx2 + (qn - 2.0 * q + qs) * g.idy2 +
-                         (qt - 2.0 * q + qb) * g.idz2;
-      const double ue = 0.5 * ((double)u[c] + (double)u[c + sxy]);
-      const double uw = 0.5 * ((double)u[c - 1] + (double)u[c - 1 + sxy]);
-      const double cx = (flux(ue, q, qe, gamma) - flux(uw, qw, q, gamma)) * g.idx;
-      const double vn = 0.5 * ((double)v[c] + (double)v[c + sxy]);
-      const double vs = 0.5 * ((double)v[c - sx] + (double)v[c - sx + sxy]);
-      const double cy = (flux(vn, q, qn, gamma) - flux(vs, qs, q, gamma)) * g.idy;
-      const double cz = (flux(0.5 * (q + qt), q, qt, gamma) - flux(0.5 * (qb + q), qb, q, gamma)) * g.idz;
-      const double f = gz + (HAS_F ? (double)fz[c] : 0.0);
-      Hv = q + dt * (nu * lap - cx - cy - cz + f);
-    }
+    const double Fv = F_at<T, HAS_F>(g, c, u, v, w, fx, dt, nu, gamma, gx);
+    const double Gv = G_at<T, HAS_F>(g, c, u, v, w, fy, dt, nu, gamma, gy);
+    const double Hv = H_at<T, HAS_F>(g, c, u, v, w, fz, dt, nu, gamma, gz);
     if (ci <= g.hi[0]) F[c] = T(Fv);
     if (cj <= g.hi[1]) G[c] = T(Gv);
     if (ck <= g.hi[2]) H[c] = T(Hv);
