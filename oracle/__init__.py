@@ -49,6 +49,7 @@ class _Cfg(ctypes.Structure):
         ("g", ctypes.c_double * 3),
         ("eta", ctypes.c_double),
         ("advective", ctypes.c_int),
+        ("stages", ctypes.c_int),
     ]
 
 
@@ -141,6 +142,10 @@ class Oracle:
             c.g[q] = float(g[q])
         c.eta = float(params.get("eta", 1e-2))
         c.advective = 1 if params.get("convection", "conservative") == "advective" else 0
+        integ = params.get("integrator", "euler")
+        if integ not in ("euler", "rk2"):
+            raise ValueError(f"integrator must be 'euler' or 'rk2', not {integ!r}")
+        c.stages = 2 if integ == "rk2" else 1
         self.cfg = c
         self.shape = (c.nz + 2, c.ny + 2, c.nx + 2)
         self.u, self.v, self.w, self.p = (np.zeros(self.shape) for _ in range(4))

@@ -424,38 +424,85 @@ double nso_dt(const nso_cfg *c, const double *u, const double *v, const double *
 }
 
 /* ------------------------------------------------------------------------ */
-/* One step n -> n+1: dt, velocity BC, predictor, rhs, Poisson solve,
- * pressure ghosts, projection, velocity BC.                                */
+/* One projected Euler stage from the current velocity with step dt:
+ * velocity BC, predictor, rhs, Poisson solve, pressure ghosts, projection,
+ * velocity BC.  Returns the sweeps; *res, *outer, *thr of the solve.      */
+static int euler_stage(const nso_cfg *c, double dt, double *u, double *v, double *w, double *p,
+                       const double *fx, const double *fy, const double *fz, double *work, int mode,
+                       double *res, int *outer, double *thr) {
+  long ntot = SX * SY * ((long)c->nz + 2);
+  double *F = work, *G = work + ntot, *H = work + 2 * ntot, *rhs = work + 3 * ntot;
+  nso_bc_vel(c, u, v, w);
+  nso_fgh(c, dt, u, v, w, fx, fy, fz, F, G, H);
+  nso_rhs(c, dt, F, G, H, rhs);
+  *res = 0.0;
+  *outer = 0;
+  int sweeps;
+  if (mode == 0) sweeps = nso_sor_solve(c, p, rhs, res);
+  else sweeps = nso_sor_defect(c, p, rhs, res, outer);
+  nso_p_ghosts(c, p);
+  nso_project(c, dt, F, G, H, p, u, v, w);
+  nso_bc_vel(c, u, v, w);
+  double rr = nso_rms(c, rhs);
+  *thr = c->tol * (rr > 1e-300 ? rr : 1e-300);
+  return sweeps;
+}
+
+/* One step n -> n+1.  dt from u^n (adaptive) or fixed.  Euler: one stage.
+ * Two stages (the second-order strong-stability-preserving Runge-Kutta
+ * method of Heun, the method-of-lines form: y1 = y + dt f(y),
+ * y+ = (y + y1 + dt f(y1)) / 2): u1 = P(u^n + dt N(u^n)),
+ * u2 = P(u1 + dt N(u1)), u^{n+1} = (u^n + u2) / 2 on every entry, then the
+ * velocity BC.  P is linear and u^n divergence-free, so the average is too;
+ * the pressure left is the second stage's.                                  */
 int nso_run(const nso_cfg *c, double *u, double *v, double *w, double *p,
             const double *fx, const double *fy, const double *fz,
             double *work, int nsteps, int mode, nso_stats *st) {
   long ntot = SX * SY * ((long)c->nz + 2);
-  double *F = work, *G = work + ntot, *H = work + 2 * ntot, *rhs = work + 3 * ntot;
+  double *save = NULL;
+  if (c->stages == 2) {
+    save = (double *)malloc(3 * ntot * sizeof(double));
+    if (!save) return -5;
+  }
+  int rc = 0;
   for (int s = 0; s < nsteps; s++) {
     double dt = c->dt > 0.0 ? c->dt : nso_dt(c, u, v, w);
-    nso_bc_vel(c, u, v, w);
-    nso_fgh(c, dt, u, v, w, fx, fy, fz, F, G, H);
-    nso_rhs(c, dt, F, G, H, rhs);
-    double res = 0.0;
-    int outer = 0, sweeps;
-    if (mode == 0) sweeps = nso_sor_solve(c, p, rhs, &res);
-    else sweeps = nso_sor_defect(c, p, rhs, &res, &outer);
-    nso_p_ghosts(c, p);
-    nso_project(c, dt, F, G, H, p, u, v, w);
-    nso_bc_vel(c, u, v, w);
-    if (!isfinite(res)) return -4;
-    double rr = nso_rms(c, rhs);
-    double thr = c->tol * (rr > 1e-300 ? rr : 1e-300);
+    if (save) {
+      memcpy(save, u, ntot * sizeof(double));
+      memcpy(save + ntot, v, ntot * sizeof(double));
+      memcpy(save + 2 * ntot, w, ntot * sizeof(double));
+    }
+    double res, thr;
+    int outer;
+    int sweeps = euler_stage(c, dt, u, v, w, p, fx, fy, fz, work, mode, &res, &outer, &thr);
+    int unconv = res > thr;
+    if (save && isfinite(res)) {
+      double res2, thr2;
+      int outer2;
+      sweeps += euler_stage(c, dt, u, v, w, p, fx, fy, fz, work, mode, &res2, &outer2, &thr2);
+      unconv |= res2 > thr2;
+      if (outer2 > outer) outer = outer2;
+      res = res2;
+      double *q[3] = {u, v, w};
+      for (int f = 0; f < 3; f++)
+        for (long e = 0; e < ntot; e++) q[f][e] = 0.5 * (save[f * ntot + e] + q[f][e]);
+      nso_bc_vel(c, u, v, w);
+    }
+    if (!isfinite(res)) {
+      rc = -4;
+      break;
+    }
     st->t += dt;
     st->dt_last = dt;
     st->res_last = res;
     st->sweeps_total += sweeps;
     if (sweeps > st->sweeps_max) st->sweeps_max = sweeps;
     if (outer > st->outer_max) st->outer_max = outer;
-    if (res > thr) st->steps_unconverged++;
+    if (unconv) st->steps_unconverged++;
     st->steps++;
   }
-  return 0;
+  free(save);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */

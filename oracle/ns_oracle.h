@@ -52,6 +52,9 @@ typedef struct {
   double eta;           /* defect-correction inner tolerance factor */
   int advective;        /* 0: conservative fluxes blended by gamma; 1: advective form
                            weighted by alpha = gamma (see nso_fgh) */
+  int stages;           /* time integrator: 0 or 1 = explicit Euler with projection;
+                           2 = two-stage SSP Runge-Kutta (Heun) whose stages are
+                           projected Euler steps with the same dt (see nso_run) */
 } nso_cfg;
 
 typedef struct {
@@ -98,7 +101,10 @@ double nso_dt(const nso_cfg *c, const double *u, const double *v,
               const double *w);
 /* nsteps full steps; work holds 4 padded fields (F, G, H, rhs).  mode 0 =
  * plain SOR, 1 = defect-correction form.  Returns 0, or -4 when a
- * non-finite residual appears (st->steps counts completed steps). */
+ * non-finite residual appears (st->steps counts completed steps), -5 when
+ * the two-stage integrator cannot get its scratch memory.  With two stages
+ * a step's sweeps are those of both solves, its residual the second's, and
+ * it counts as unconverged when either solve stopped above its threshold. */
 int nso_run(const nso_cfg *c, double *u, double *v, double *w, double *p,
             const double *fx, const double *fy, const double *fz,
             double *work, int nsteps, int mode, nso_stats *st);
