@@ -81,9 +81,16 @@ enum {
                             pass of sweeps, polled by the host, instead of the persistent launch */
   NS_GENERATED = 8,      /* one instance: the predictor and the projection are the kernels the
                             build generates from the kernel descriptors (same results) */
-  NS_ADVECTIVE = 16      /* one instance: the convective term in advective form weighted by
+  NS_ADVECTIVE = 16,     /* one instance: the convective term in advective form weighted by
                             alpha = gamma (SOLA / NASA-VOF2D) instead of conservative fluxes
                             blended by gamma; not with NS_GENERATED or checkpoint_every */
+  NS_RK2 = 32            /* one instance: two-stage SSP Runge-Kutta (Heun) time integration,
+                            the method-of-lines integrator of the Cactus framework the paper
+                            builds on ("Cactus Computational Framework"): two projected Euler
+                            stages with the same dt (the adaptive dt from u^n), then
+                            u^{n+1} = (u^n + u^(2)) / 2 and the boundary fill; the pressure is
+                            the second stage's.  A step's sweeps count both solves.  Not with
+                            checkpoint_every or ns_step_noalloc */
 };
 
 typedef struct {

@@ -19,7 +19,7 @@ FIELD_IDS = {"u": NS_U, "v": NS_V, "w": NS_W, "p": NS_P, "fx": NS_FX, "fy": NS_F
              "F": NS_F, "G": NS_G, "H": NS_H, "rhs": NS_RHS}
 NS_BC_WALL, NS_BC_PERIODIC = 0, 1
 NS_FP64, NS_MIXED = 0, 1
-NS_ALLOW_UNSTABLE, NS_TIMING, NS_BATCH_LAUNCHES, NS_GENERATED, NS_ADVECTIVE = 1, 2, 4, 8, 16
+NS_ALLOW_UNSTABLE, NS_TIMING, NS_BATCH_LAUNCHES, NS_GENERATED, NS_ADVECTIVE, NS_RK2 = 1, 2, 4, 8, 16, 32
 NS_T_BC, NS_T_FGH, NS_T_RHS, NS_T_SOR, NS_T_DEFECT, NS_T_PROJECT, NS_T_OTHER, NS_T_COUNT = 0, 1, 2, 3, 4, 5, 6, 8
 EXPORTED = ("ns_params_default", "ns_create", "ns_set_state", "ns_step", "ns_get_state",
             "ns_backward", "ns_get_timing", "ns_destroy", "ns_last_error", "ns_step_noalloc")

@@ -302,6 +302,20 @@ k_fgh_adv(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __r
     fgh_adv_cells<T, false>(g, zr, own_blk(), u, v, w, fx, fy, fz, F, G, H, ctl, nu, alpha, gx, gy, gz);
 }
 
+
+// u = (a + u) / 2 (and v, w) on every entry of the padded fields: the
+// combination of the two-stage Runge-Kutta step.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_average(long n, const T* __restrict__ a0, const T* __restrict__ a1, const T* __restrict__ a2,
+          T* __restrict__ q0, T* __restrict__ q1, T* __restrict__ q2) {
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+    q0[e] = T(0.5 * ((double)a0[e] + (double)q0[e]));
+    q1[e] = T(0.5 * ((double)a1[e] + (double)q1[e]));
+    q2[e] = T(0.5 * ((double)a2[e] + (double)q2[e]));
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -383,6 +397,15 @@ hipError_t launch_rhs(hipStream_t st, const Geo& g, const T* F, const T* G, cons
 }
 
 template <class T>
+hipError_t launch_average(hipStream_t st, const Geo& g, const T* a0, const T* a1, const T* a2, T* q0, T* q1, T* q2) {
+  const long n = g.ntot;
+  long nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  k_average<T><<<(unsigned)nb, 256, 0, st>>>(n, a0, a1, a2, q0, q1, q2);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_project(hipStream_t st, const Geo& g, const T* F, const T* G, const T* H,
                           const double* p, T* u, T* v, T* w, const Ctl* ctl, double unit_dt) {
   k_project<T><<<cell_grid(g, 0), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, 0), F, G, H, p, u, v, w, g, ctl, unit_dt != 0.0);
@@ -434,6 +457,7 @@ hipError_t launch_mask_unknowns(hipStream_t st, const Geo& g, double* q, int com
                                     double, const double[3]);                                       \
   template hipError_t launch_rhs<T>(hipStream_t, const Geo&, const T*, const T*, const T*, T*,      \
                                     Ctl*, double*, double, double);                                 \
+  template hipError_t launch_average<T>(hipStream_t, const Geo&, const T*, const T*, const T*, T*, T*, T*); \
   template hipError_t launch_project<T>(hipStream_t, const Geo&, const T*, const T*, const T*,      \
                                         const double*, T*, T*, T*, const Ctl*, double);             \
   template hipError_t launch_umax<T>(hipStream_t, const Geo&, const T*, const T*, const T*, Ctl*,   \

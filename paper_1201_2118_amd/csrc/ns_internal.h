@@ -64,6 +64,10 @@ template <class T> hipError_t launch_fgh(hipStream_t st, const Geo& g, const T* 
                                         const T* w, const T* fx, const T* fy, const T* fz,
                                         T* F, T* G, T* H, const Ctl* ctl, double re, double gamma,
                                         const double gforce[3]);
+// q = (a + q) / 2 on every entry of three padded fields (the two-stage
+// Runge-Kutta combination).
+template <class T> hipError_t launch_average(hipStream_t st, const Geo& g, const T* a0, const T* a1, const T* a2,
+                                            T* q0, T* q1, T* q2);
 template <class T> hipError_t launch_rhs(hipStream_t st, const Geo& g, const T* F, const T* G,
                                         const T* H, T* rhs, Ctl* ctl, double* part, double tol,
                                         double dt_scale_one);

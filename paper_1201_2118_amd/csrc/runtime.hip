@@ -53,6 +53,7 @@ struct Inst {
   void* frc[3] = {nullptr, nullptr, nullptr};
   float* e[2] = {nullptr, nullptr};
   float* r = nullptr;
+  void* save[3] = {nullptr, nullptr, nullptr};  // NS_RK2: u^n, v^n, w^n
   double* part = nullptr;
   Ctl* ctl = nullptr;
   ns_stats st{};
@@ -226,12 +227,14 @@ ns_status validate(const ns_params& p, int idx) {
       if (!std::isfinite(p.wall_vel[f][c])) return bad("wall velocities must be finite");
   for (int c = 0; c < 3; c++)
     if (!std::isfinite(p.g[c])) return bad("body force must be finite");
-  if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING | NS_BATCH_LAUNCHES | NS_GENERATED | NS_ADVECTIVE))
+  if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING | NS_BATCH_LAUNCHES | NS_GENERATED | NS_ADVECTIVE | NS_RK2))
     return bad("unknown flag bits");
   if ((p.flags & NS_ADVECTIVE) && (p.flags & NS_GENERATED))
     return bad("the generated predictor has the conservative form (NS_ADVECTIVE with NS_GENERATED)");
   if ((p.flags & NS_ADVECTIVE) && p.checkpoint_every > 0)
     return bad("the adjoint covers the conservative form only (NS_ADVECTIVE with checkpoint_every)");
+  if ((p.flags & NS_RK2) && p.checkpoint_every > 0)
+    return bad("the adjoint covers the Euler step only (NS_RK2 with checkpoint_every)");
   if (!(p.tile[0] == -1 || p.tile[0] == 0 || p.tile[0] == 4 || p.tile[0] == 8 || p.tile[0] == 12 ||
         p.tile[0] == 16 || p.tile[0] == 24 || p.tile[0] == 32))
     return bad("tile[0] must be -1, 0, 4, 8, 12, 16, 24 or 32");
@@ -575,6 +578,7 @@ void free_inst(Inst& I) {
   (void)hipFree(I.F); (void)hipFree(I.G); (void)hipFree(I.H); (void)hipFree(I.rhs);
   for (int c = 0; c < 3; c++) (void)hipFree(I.frc[c]);
   (void)hipFree(I.e[0]); (void)hipFree(I.e[1]); (void)hipFree(I.r);
+  for (int c = 0; c < 3; c++) (void)hipFree(I.save[c]);
   (void)hipFree(I.part);  // I.ctl lives in the handle's ctl_all
   for (auto& c : I.ck) free_state(c);
   I.ck.clear();
@@ -808,14 +812,14 @@ ns_status solve_mixed(ns_solver* s, int idx, int* sweeps, int* outer) {
 // ---- one step ------------------------------------------------------------------
 // Stages before the Poisson solve: dt, boundary fill, predictor, rhs.
 template <class T>
-ns_status step_pre(ns_solver* s, int idx, State& S) {
+ns_status step_pre(ns_solver* s, int idx, State& S, bool new_dt = true) {
   Inst& I = s->in[idx];
   const Geo& g = I.g;
   const ns_params& p = I.prm;
   T* u = (T*)S.u;
   T* v = (T*)S.v;
   T* w = (T*)S.w;
-  if (p.dt <= 0) {
+  if (p.dt <= 0 && new_dt) {
     Timed t(s, NS_T_OTHER);
     HCK(s, launch_umax<T>(s->stream, g, u, v, w, I.ctl, I.part, p.re, p.tau, p.wall_vel));
   }
@@ -890,9 +894,71 @@ ns_status step_post(ns_solver* s, int idx, State& S, int sweeps, int outer, bool
   return step_account(s, idx, sweeps, outer, account);
 }
 
+// Two-stage SSP Runge-Kutta (Heun) step of a single-domain handle: u^n
+// saved, two projected Euler stages with the step size of the first (the
+// second skips the adaptive rule), u^{n+1} = (u^n + u^(2)) / 2 on every
+// entry, boundary fill.  A step's sweeps are both solves'; it counts as
+// unconverged when either solve stopped above its threshold; the residual
+// and pressure are the second stage's.
+template <class T>
+ns_status step_rk2(ns_solver* s, int idx, State& S, bool account) {
+  Inst& I = s->in[idx];
+  {
+    Timed t(s, NS_T_OTHER);
+    HCK(s, hipMemcpyAsync(I.save[0], S.u, I.bytes, hipMemcpyDeviceToDevice, s->stream));
+    HCK(s, hipMemcpyAsync(I.save[1], S.v, I.bytes, hipMemcpyDeviceToDevice, s->stream));
+    HCK(s, hipMemcpyAsync(I.save[2], S.w, I.bytes, hipMemcpyDeviceToDevice, s->stream));
+  }
+  int sweeps = 0, outer = 0;
+  bool unconv = false;
+  for (int stage = 0; stage < 2; stage++) {
+    ns_status e = step_pre<T>(s, idx, S, stage == 0);
+    if (e != NS_OK) return e;
+    int sw = 0, ou = 0;
+    e = I.mixed ? solve_mixed(s, idx, &sw, &ou) : solve_fp64(s, idx, S.p, &S.pcur, &sw);
+    if (e != NS_OK) return e;
+    e = step_post<T>(s, idx, S, sw, ou, false);
+    if (e != NS_OK) return e;
+    sweeps += sw;
+    outer = std::max(outer, ou);
+    unconv |= s->hctl[idx].res > s->hctl[idx].thr;
+    if (s->timing) {
+      HCK(s, hipStreamSynchronize(s->stream));
+      harvest(s, I.mixed ? 1 << 30 : sw + 1);
+    }
+  }
+  {
+    Timed t(s, NS_T_OTHER);
+    HCK(s, launch_average<T>(s->stream, I.g, (const T*)I.save[0], (const T*)I.save[1], (const T*)I.save[2],
+                             (T*)S.u, (T*)S.v, (T*)S.w));
+  }
+  {
+    Timed t(s, NS_T_BC);
+    HCK(s, launch_bc_vel<T>(s->stream, I.g, (T*)S.u, (T*)S.v, (T*)S.w, I.prm.wall_vel));
+  }
+  if (s->timing) {
+    HCK(s, hipStreamSynchronize(s->stream));
+    harvest(s, 1 << 30);
+  }
+  if (account) {
+    const Ctl h = s->hctl[idx];
+    ns_stats& st = I.st;
+    st.t += h.dt;
+    st.dt_last = h.dt;
+    st.res_last = h.res;
+    st.sweeps_total += sweeps;
+    st.sweeps_max = std::max(st.sweeps_max, sweeps);
+    st.outer_max = std::max(st.outer_max, outer);
+    if (unconv) st.steps_unconverged++;
+    st.steps++;
+  }
+  return NS_OK;
+}
+
 template <class T>
 ns_status step_inst(ns_solver* s, int idx, State& S, bool account) {
   Inst& I = s->in[idx];
+  if (I.prm.flags & NS_RK2) return step_rk2<T>(s, idx, S, account);
   ns_status e = step_pre<T>(s, idx, S);
   if (e != NS_OK) return e;
   int sweeps = 0, outer = 0;
@@ -1750,8 +1816,8 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
   for (int i = 0; i < n_instances; i++) {
     ns_status st = validate(params[i], i);
     if (st != NS_OK) return st;
-    if ((params[i].flags & (NS_GENERATED | NS_ADVECTIVE)) && n_instances > 1)
-      return fail(nullptr, NS_E_INVALID, "NS_GENERATED and NS_ADVECTIVE need a handle of one instance");
+    if ((params[i].flags & (NS_GENERATED | NS_ADVECTIVE | NS_RK2)) && n_instances > 1)
+      return fail(nullptr, NS_E_INVALID, "NS_GENERATED, NS_ADVECTIVE and NS_RK2 need a handle of one instance");
   }
   ns_solver* s = new ns_solver();
   if (hipGetDevice(&s->device) != hipSuccess) {
@@ -1792,6 +1858,8 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
       if (e == hipSuccess) e = dmalloc((void**)&I.r, (size_t)I.g.ntot * 4);
     }
     if (e == hipSuccess) e = dmalloc((void**)&I.part, reduce_blocks(I.g) * sizeof(double));
+    if (I.prm.flags & NS_RK2)
+      for (int c = 0; c < 3 && e == hipSuccess; c++) e = dmalloc(&I.save[c], I.bytes);
     I.ctl = s->ctl_all + i;
     if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? NS_E_OOM : NS_E_DEVICE,
                                      std::string("allocation failed: ") + hipGetErrorString(e));
@@ -2124,6 +2192,7 @@ ns_status ns_step_noalloc(const ns_params* params, double* u, double* v, double*
   if (params->precision != NS_FP64) return fail(nullptr, NS_E_INVALID, "ns_step_noalloc: NS_FP64 only");
   if (params->checkpoint_every != 0) return fail(nullptr, NS_E_INVALID, "ns_step_noalloc: no recording");
   if (params->flags & NS_TIMING) return fail(nullptr, NS_E_INVALID, "ns_step_noalloc: no stage timers");
+  if (params->flags & NS_RK2) return fail(nullptr, NS_E_INVALID, "ns_step_noalloc: Euler steps only");
   if (nsteps < 0) return fail(nullptr, NS_E_INVALID, "nsteps must be >= 0");
   if (!u || !v || !w || !p) return fail(nullptr, NS_E_INVALID, "u, v, w and p must be device pointers");
   const Geo g = make_geo(*params);

@@ -44,6 +44,11 @@ def make_params(prm: dict) -> abi.ns_params:
     p.flags = int(prm.get("flags", 0))
     if prm.get("convection", "conservative") == "advective":
         p.flags |= abi.NS_ADVECTIVE
+    integ = prm.get("integrator", "euler")
+    if integ not in ("euler", "rk2"):
+        raise ValueError(f"integrator must be 'euler' or 'rk2', not {integ!r}")
+    if integ == "rk2":
+        p.flags |= abi.NS_RK2
     tile = prm.get("tile", (0, 0))
     p.tile[0], p.tile[1] = int(tile[0]), int(tile[1])
     return p

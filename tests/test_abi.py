@@ -146,3 +146,21 @@ def test_advective_form_refuses_unsupported_combinations():
     h = ctypes.c_void_p()
     assert abi.ns_create(arr, 2, None, h) == abi.NS_E_INVALID
     assert "one instance" in abi.ns_last_error(None)
+
+
+def test_rk2_refuses_unsupported_combinations():
+    """NS_RK2: one instance, not with recording for the adjoint, not through
+    ns_step_noalloc (host-side validation); an unknown integrator name is
+    refused by the binding."""
+    prm = dict(W.cavity(8), integrator="rk2")
+    assert make_params(prm).flags & abi.NS_RK2
+    assert _create(dict(prm, checkpoint_every=2))[0] == abi.NS_E_INVALID
+    assert "NS_RK2" in abi.ns_last_error(None)
+    arr = (abi.ns_params * 2)(make_params(prm), make_params(prm))
+    h = ctypes.c_void_p()
+    assert abi.ns_create(arr, 2, None, h) == abi.NS_E_INVALID
+    assert "one instance" in abi.ns_last_error(None)
+    code = abi.ns_step_noalloc(make_params(prm), 1, 1, 1, 1, 1, None, None)
+    assert code == abi.NS_E_INVALID and "Euler" in abi.ns_last_error(None)
+    with pytest.raises(ValueError):
+        make_params(dict(W.cavity(8), integrator="rk4"))
