@@ -79,11 +79,13 @@ enum {
   NS_TIMING = 2,         /* record per-stage GPU times (ns_get_timing) */
   NS_BATCH_LAUNCHES = 4, /* several instances (flag of instance 0): one launch per stage and per
                             pass of sweeps, polled by the host, instead of the persistent launch */
-  NS_GENERATED = 8,      /* one instance: the predictor and the projection are the kernels the
-                            build generates from the kernel descriptors (same results) */
+  NS_GENERATED = 8,      /* one instance: the projection too is the kernel the build generates
+                            from its kernel descriptor (UPDATE_VELOCITY) instead of the
+                            hand-written one (same results); the predictor of the conservative
+                            form is always the generated PREDICT_VELOCITY kernel */
   NS_ADVECTIVE = 16,     /* one instance: the convective term in advective form weighted by
                             alpha = gamma (SOLA / NASA-VOF2D) instead of conservative fluxes
-                            blended by gamma; not with NS_GENERATED or checkpoint_every */
+                            blended by gamma; not with checkpoint_every */
   NS_RK2 = 32            /* one instance: two-stage SSP Runge-Kutta (Heun) time integration,
                             the method-of-lines integrator of the Cactus framework the paper
                             builds on ("Cactus Computational Framework"): two projected Euler

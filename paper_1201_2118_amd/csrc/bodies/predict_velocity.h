@@ -11,6 +11,7 @@ namespace gen {
 
 template <class K>
 __device__ __forceinline__ double body_force(const K& x, double gc, int c) {
+#pragma clang fp contract(on)
   if constexpr (K::has_BODY_FORCE)
     return gc + (double)(c == 0 ? x.fx() : (c == 1 ? x.fy() : x.fz()));
   else
@@ -19,6 +20,7 @@ __device__ __forceinline__ double body_force(const K& x, double gc, int c) {
 
 template <class K>
 __device__ __forceinline__ void PREDICT_VELOCITY_body(const K& x) {
+#pragma clang fp contract(on)  // as in the hand-written predictor
   const Geo& g = x.g;
   const double dt = x.dt, nu = x.nu, gamma = x.gamma;
   double Fv, Gv, Hv;

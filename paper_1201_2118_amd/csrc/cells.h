@@ -24,7 +24,12 @@ namespace {
 // t = the d-velocity interpolated to that point (mean of the two d-faces at
 // pos and pos + e_c; for d == c the mean of q and q[+d]).
 // F_c = q + dt (nu lap q - sum_d (flux_hi - flux_lo)/h_d + g_c + f_c).
+// The predictor's expressions fuse multiply-adds only within one source
+// expression (contract(on)), so every kernel that inlines them (the
+// hand-written ones, the generated ones) rounds each value alike whatever
+// code surrounds it.
 __device__ __forceinline__ double flux(double t, double a, double b, double gamma) {
+#pragma clang fp contract(on)
   return 0.5 * (t * (a + b) + gamma * fabs(t) * (a - b));
 }
 
@@ -36,6 +41,7 @@ template <class T, bool HAS_F>
 __device__ __forceinline__ double F_at(const Geo& g, long c, const T* __restrict__ u, const T* __restrict__ v,
                                        const T* __restrict__ w, const T* __restrict__ fx, double dt, double nu,
                                        double gamma, double gx) {
+#pragma clang fp contract(on)
   const long sx = g.sx, sxy = g.sxy;
   const double q = u[c], qe = u[c + 1], qw = u[c - 1], qn = u[c + sx], qs = u[c - sx], qt = u[c + sxy],
                qb = u[c - sxy];
@@ -54,6 +60,7 @@ template <class T, bool HAS_F>
 __device__ __forceinline__ double G_at(const Geo& g, long c, const T* __restrict__ u, const T* __restrict__ v,
                                        const T* __restrict__ w, const T* __restrict__ fy, double dt, double nu,
                                        double gamma, double gy) {
+#pragma clang fp contract(on)
   const long sx = g.sx, sxy = g.sxy;
   const double q = v[c], qe = v[c + 1], qw = v[c - 1], qn = v[c + sx], qs = v[c - sx], qt = v[c + sxy],
                qb = v[c - sxy];
@@ -72,6 +79,7 @@ template <class T, bool HAS_F>
 __device__ __forceinline__ double H_at(const Geo& g, long c, const T* __restrict__ u, const T* __restrict__ v,
                                        const T* __restrict__ w, const T* __restrict__ fz, double dt, double nu,
                                        double gamma, double gz) {
+#pragma clang fp contract(on)
   const long sx = g.sx, sxy = g.sxy;
   const double q = w[c], qe = w[c + 1], qw = w[c - 1], qn = w[c + sx], qs = w[c - sx], qt = w[c + sxy],
                qb = w[c - sxy];

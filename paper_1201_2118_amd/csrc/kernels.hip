@@ -163,18 +163,6 @@ dim3 face_grid(const Geo& g, dim3 blk, int zdim) {
 
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_fgh(int zr, const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
-      const T* __restrict__ fx, const T* __restrict__ fy, const T* __restrict__ fz,
-      T* __restrict__ F, T* __restrict__ G, T* __restrict__ H, Geo g, const Ctl* __restrict__ ctl,
-      double nu, double gamma, double gx, double gy, double gz) {
-  if (fx)
-    fgh_cells<T, true>(g, zr, own_blk(), u, v, w, fx, fy, fz, F, G, H, ctl, nu, gamma, gx, gy, gz);
-  else
-    fgh_cells<T, false>(g, zr, own_blk(), u, v, w, fx, fy, fz, F, G, H, ctl, nu, gamma, gx, gy, gz);
-}
-
-template <class T>
-__global__ void __launch_bounds__(kBlock)
 k_rhs(int zr, const T* __restrict__ F, const T* __restrict__ G, const T* __restrict__ H,
       T* __restrict__ rhs, Geo g, Ctl* ctl, double* part, double tol, int unit_dt) {
   __shared__ double sh[16];
@@ -354,15 +342,6 @@ hipError_t launch_periodic(hipStream_t st, const Geo& g, T* q, int axis) {
 }
 
 template <class T>
-hipError_t launch_fgh(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, const T* fx,
-                      const T* fy, const T* fz, T* F, T* G, T* H, const Ctl* ctl, double re,
-                      double gamma, const double gf[3]) {
-  k_fgh<T><<<cell_grid(g, 0), dim3(kCellX, kCellY), 0, st>>>(cell_zrun(g, 0), u, v, w, fx, fy, fz, F, G, H, g, ctl, 1.0 / re,
-                                                     gamma, gf[0], gf[1], gf[2]);
-  return hipGetLastError();
-}
-
-template <class T>
 hipError_t launch_fgh_advective(hipStream_t st, const Geo& g, const T* u, const T* v, const T* w, const T* fx,
                                 const T* fy, const T* fz, T* F, T* G, T* H, const Ctl* ctl, double re, double alpha,
                                 const double gf[3]) {
@@ -452,9 +431,6 @@ hipError_t launch_mask_unknowns(hipStream_t st, const Geo& g, double* q, int com
   template hipError_t launch_bc_vel<T>(hipStream_t, const Geo&, T*, T*, T*, const double[6][3]);    \
   template hipError_t launch_p_ghosts<T>(hipStream_t, const Geo&, T*);                              \
   template hipError_t launch_periodic<T>(hipStream_t, const Geo&, T*, int);                         \
-  template hipError_t launch_fgh<T>(hipStream_t, const Geo&, const T*, const T*, const T*,          \
-                                    const T*, const T*, const T*, T*, T*, T*, const Ctl*, double,   \
-                                    double, const double[3]);                                       \
   template hipError_t launch_rhs<T>(hipStream_t, const Geo&, const T*, const T*, const T*, T*,      \
                                     Ctl*, double*, double, double);                                 \
   template hipError_t launch_average<T>(hipStream_t, const Geo&, const T*, const T*, const T*, T*, T*, T*); \

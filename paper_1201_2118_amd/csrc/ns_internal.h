@@ -60,10 +60,6 @@ inline bool shape_is_pass(const SorShape& s) { return s.ty >= 16; }
 template <class T> hipError_t launch_bc_vel(hipStream_t st, const Geo& g, T* u, T* v, T* w,
                                            const double wall[6][3]);
 template <class T> hipError_t launch_p_ghosts(hipStream_t st, const Geo& g, T* p);
-template <class T> hipError_t launch_fgh(hipStream_t st, const Geo& g, const T* u, const T* v,
-                                        const T* w, const T* fx, const T* fy, const T* fz,
-                                        T* F, T* G, T* H, const Ctl* ctl, double re, double gamma,
-                                        const double gforce[3]);
 // q = (a + q) / 2 on every entry of three padded fields (the two-stage
 // Runge-Kutta combination).
 template <class T> hipError_t launch_average(hipStream_t st, const Geo& g, const T* a0, const T* a1, const T* a2,

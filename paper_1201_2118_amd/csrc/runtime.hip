@@ -229,8 +229,6 @@ ns_status validate(const ns_params& p, int idx) {
     if (!std::isfinite(p.g[c])) return bad("body force must be finite");
   if (p.flags & ~(NS_ALLOW_UNSTABLE | NS_TIMING | NS_BATCH_LAUNCHES | NS_GENERATED | NS_ADVECTIVE | NS_RK2))
     return bad("unknown flag bits");
-  if ((p.flags & NS_ADVECTIVE) && (p.flags & NS_GENERATED))
-    return bad("the generated predictor has the conservative form (NS_ADVECTIVE with NS_GENERATED)");
   if ((p.flags & NS_ADVECTIVE) && p.checkpoint_every > 0)
     return bad("the adjoint covers the conservative form only (NS_ADVECTIVE with checkpoint_every)");
   if ((p.flags & NS_RK2) && p.checkpoint_every > 0)
@@ -829,15 +827,14 @@ ns_status step_pre(ns_solver* s, int idx, State& S, bool new_dt = true) {
   }
   {
     Timed t(s, NS_T_FGH);
+    // the conservative predictor is the kernel generated from its descriptor
+    // (streamed through z with the velocity in an LDS plane ring)
     if (p.flags & NS_ADVECTIVE)
       HCK(s, launch_fgh_advective<T>(s->stream, g, u, v, w, (const T*)I.frc[0], (const T*)I.frc[1],
                                      (const T*)I.frc[2], (T*)I.F, (T*)I.G, (T*)I.H, I.ctl, p.re, p.gamma, p.g));
-    else if (p.flags & NS_GENERATED)
+    else
       HCK(s, launch_gen_fgh<T>(s->stream, g, u, v, w, (const T*)I.frc[0], (const T*)I.frc[1], (const T*)I.frc[2],
                                (T*)I.F, (T*)I.G, (T*)I.H, I.ctl, p.re, p.gamma, p.g));
-    else
-      HCK(s, launch_fgh<T>(s->stream, g, u, v, w, (const T*)I.frc[0], (const T*)I.frc[1], (const T*)I.frc[2],
-                           (T*)I.F, (T*)I.G, (T*)I.H, I.ctl, p.re, p.gamma, p.g));
   }
   {
     Timed t(s, NS_T_RHS);

@@ -20,20 +20,28 @@ Grammar (parsing expression grammar; ``#`` starts a comment):
     attr      <- NAME '=' (STRING / WORD)
     names     <- NAME (',' NAME)*
 
-Kernel attributes: TYPE (3DBLOCK), STENCIL ("x-,x+,y-,y+,z-,z+" halo cells,
-0 or 1 each: the fields carry one ghost layer), TILE ("x,y,z" cells per
-workgroup tile; x * y threads, x a multiple of 64, each thread marching z
-cells).  Variable attributes: CACHED (YES: staged in LDS with the halo),
+Kernel attributes: TYPE (3DBLOCK or 3DSTREAM), STENCIL ("x-,x+,y-,y+,z-,z+"
+halo cells, 0 or 1 each: the fields carry one ghost layer), TILE ("x,y,z"
+cells per workgroup tile; x * y threads, x a multiple of 64, each thread
+marching z cells).  Variable attributes: CACHED (YES: staged in LDS with the halo),
 INTENT (IN, OUT, INOUT, SEPARATEINOUT), STORAGE (FIELD: the storage type of
 the fields, FP64), OPTIONAL (YES: the group may be absent; a template flag).
 Parameter attributes: SOURCE (VALUE: an FP64 kernel argument, CONTROL: the
 field of the same name of the domain's control block, read on the device).
 
-The generated kernel for tile (bx, by, bz) of a domain: every thread of
-the workgroup loads the cached variables' box (tile plus halo) into LDS,
-x fastest (one wave reads 64 consecutive x), with positions clamped to the
-padded array; after one barrier thread (tx, ty) runs the body for the cells
+3DBLOCK, for tile (bx, by, bz) of a domain: every thread of the workgroup
+loads the cached variables' box (tile plus halo) into LDS, x fastest (one
+wave reads 64 consecutive x), with positions clamped to the padded array;
+after one barrier thread (tx, ty) runs the body for the cells
 (i0 + tx, j0 + ty, k0 + kz), kz = 0 .. z - 1, that are interior cells.
+
+3DSTREAM, the same tile marched plane by plane: each cached variable lives
+in a ring of z- + 1 + z+ LDS planes, each plane staged with its x / y halo;
+while the body runs on plane k, every thread holds its share of plane
+k + z+ + 1 in registers, and between two barriers it replaces plane k - z-
+in the ring.  A cached value is loaded once per tile column instead of once
+per box (the box's z halo is not re-read), and the next plane's loads are in
+flight during the current plane's arithmetic.
 """
 from __future__ import annotations
 
@@ -167,9 +175,9 @@ class _Parser:
         k = Kernel(name=self.take("WORD")[1], line=line)
         for key, (val, ln) in self.attrs().items():
             if key == "TYPE":
-                if val.upper() != "3DBLOCK":
-                    raise DescriptorError(f"line {ln}: TYPE {val} is not supported (3DBLOCK)")
-                k.type = "3DBLOCK"
+                if val.upper() not in ("3DBLOCK", "3DSTREAM"):
+                    raise DescriptorError(f"line {ln}: TYPE {val} is not supported (3DBLOCK or 3DSTREAM)")
+                k.type = val.upper()
             elif key == "STENCIL":
                 k.stencil = _ints(val, 6, ln, "STENCIL")
                 if any(h < 0 or h > 1 for h in k.stencil):
@@ -295,11 +303,17 @@ def generate(k: Kernel) -> str:
     w("  const Geo& g;")
     w("  int i, j, k;  // 1-based cell indices")
     w("  long c;       // linear index in the padded layout")
-    w("  int li;       // position of the cell in the LDS box")
+    stream = k.type == "3DSTREAM"
+    nplanes = zm + 1 + zp
+    if stream:
+        w("  int li;       // position of the cell in an LDS plane")
+        w(f"  int pl[{nplanes}];    // LDS offset of planes k - {zm} .. k + {zp} in the ring")
+    else:
+        w("  int li;       // position of the cell in the LDS box")
     for n, v in k.all_vars():
         st = _storage(v)
         if v.cached:
-            w(f"  const {st}* s_{n};  // LDS box")
+            w(f"  const {st}* s_{n};  // {'LDS plane ring' if stream else 'LDS box'}")
         if v.intent in ("IN", "INOUT"):
             w(f"  {'const ' if v.intent == 'IN' else ''}{st}* __restrict__ {n}_p;")
         elif v.intent == "OUT":
@@ -316,7 +330,11 @@ def generate(k: Kernel) -> str:
         st = _storage(v)
         rd = n if v.intent in ("IN", "INOUT") else (f"{n}_in" if v.intent == "SEPARATEINOUT" else None)
         if rd is not None:
-            if v.cached:
+            if v.cached and stream:
+                w(f"  __device__ __forceinline__ {st} {rd}(int di = 0, int dj = 0, int dk = 0) const {{")
+                w(f"    return s_{n}[pl[dk + {zm}] + li + dj * {lx} + di];")
+                w("  }")
+            elif v.cached:
                 w(f"  __device__ __forceinline__ {st} {rd}(int di = 0, int dj = 0, int dk = 0) const {{")
                 w(f"    return s_{n}[li + (dk * {ly} + dj) * {lx} + di];")
                 w("  }")
@@ -353,6 +371,119 @@ def generate(k: Kernel) -> str:
     vals = [n for p in k.parameters if not p.control for n in p.names]
     args += [f"double {n}" for n in vals]
     cached = [(n, v) for n, v in k.all_vars() if v.cached]
+    if stream:
+        _stream_kernel(k, w, tparams, targs, args, cached, lx, ly, nplanes)
+    else:
+        _block_kernel(k, w, tparams, targs, args, cached, lx, ly, lz)
+    _launcher(k, w, vals, opt)
+    return "\n".join(L)
+
+
+def _set_ctx(k, w, targs):
+    w(f"  {k.name}_ctx<{targs}> x{{g}};")
+    for n, v in k.all_vars():
+        if v.cached:
+            w(f"  x.s_{n} = s_{n};")
+        if v.intent in ("IN", "OUT", "INOUT"):
+            w(f"  x.{n}_p = {n};")
+        else:
+            w(f"  x.{n}_in_p = {n}_in;")
+            w(f"  x.{n}_out_p = {n}_out;")
+    for p in k.parameters:
+        for n in p.names:
+            w(f"  x.{n} = {'ctl->' + n if p.control else n};")
+
+
+def _stream_kernel(k, w, tparams, targs, args, cached, lx, ly, nplanes):
+    tx, ty, tz = k.tile
+    xm, xp, ym, yp, zm, zp = k.stencil
+    nthr = tx * ty
+    plane = lx * ly
+    per = (plane + nthr - 1) // nthr
+    w(f"// One {tx} x {ty} tile of {k.name} per workgroup ({tx} x {ty} threads), marching")
+    w(f"// {tz} planes; cached variables in a ring of {nplanes} LDS planes of {lx} x {ly}.")
+    w(f"template <{tparams}>")
+    w(f"__global__ void __launch_bounds__({nthr})")
+    w(f"k_{k.name}(Geo g, const Ctl* __restrict__ ctl{''.join(', ' + a for a in args)}) {{")
+    for n, v in cached:
+        w(f"  __shared__ {_storage(v)} s_{n}[{nplanes * plane}];")
+    w(f"  const int i0 = blockIdx.x * {tx} + 1, j0 = blockIdx.y * {ty} + 1;")
+    w(f"  const int k0 = blockIdx.z * {tz} + 1, k1 = min(g.nz, k0 + {tz - 1});")
+    w(f"  const int tid = threadIdx.x + {tx} * threadIdx.y;")
+    if cached:
+        w("  // this thread's entries of a staged plane (x fastest, positions clamped to")
+        w("  // the padded array: clamped entries only feed cells outside the domain)")
+        w(f"  long qo[{per}];")
+        w(f"  bool qv[{per}];")
+        w(f"#pragma unroll")
+        w(f"  for (int r = 0; r < {per}; r++) {{")
+        w(f"    const int t = tid + r * {nthr};")
+        w(f"    qv[r] = t < {plane};")
+        w(f"    const int gi = min(max(i0 - {xm} + t % {lx}, 0), g.nx + 1);")
+        w(f"    const int gj = min(max(j0 - {ym} + t / {lx}, 0), g.ny + 1);")
+        w("    qo[r] = (long)gj * g.sx + gi;")
+        w("  }")
+        w(f"  // planes k0 - {zm} .. k0 + {zp}; plane kk sits in ring slot kk % {nplanes}")
+        w(f"  for (int d = -{zm}; d <= {zp}; d++) {{")
+        w("    const long kk = min(k0 + d, g.nz + 1);")
+        w(f"    const int sl = ((k0 + d) % {nplanes}) * {plane};")
+        w(f"#pragma unroll")
+        w(f"    for (int r = 0; r < {per}; r++)")
+        w("      if (qv[r]) {")
+        for n, v in cached:
+            src = n if v.intent != "SEPARATEINOUT" else f"{n}_in"
+            w(f"        s_{n}[sl + tid + r * {nthr}] = {src}[kk * g.sxy + qo[r]];")
+        w("      }")
+        w("  }")
+        w("  __syncthreads();")
+    _set_ctx(k, w, targs)
+    w("  x.i = i0 + (int)threadIdx.x;")
+    w("  x.j = j0 + (int)threadIdx.y;")
+    w("  const bool act = x.i <= g.nx && x.j <= g.ny;")
+    w(f"  x.li = ((int)threadIdx.y + {ym}) * {lx} + (int)threadIdx.x + {xm};")
+    w("  for (int k = k0; k <= k1; k++) {")
+    if cached:
+        w("    const bool more = k < k1;  // the same in every thread")
+        w(f"    const int kn = k + {zp + 1};  // the plane staged during this step")
+        for n, v in cached:
+            w(f"    {_storage(v)} pre_{n}[{per}];")
+        w("    if (more) {")
+        w("      const long kk = min(kn, g.nz + 1);")
+        w(f"#pragma unroll")
+        w(f"      for (int r = 0; r < {per}; r++) {{")
+        for n, v in cached:
+            src = n if v.intent != "SEPARATEINOUT" else f"{n}_in"
+            w(f"        pre_{n}[r] = qv[r] ? {src}[kk * g.sxy + qo[r]] : {_storage(v)}(0);")
+        w("      }")
+        w("    }")
+    w("    if (act) {")
+    w("      x.k = k;")
+    w("      x.c = (long)k * g.sxy + (long)x.j * g.sx + x.i;")
+    if cached:
+        w(f"#pragma unroll")
+        w(f"      for (int d = 0; d < {nplanes}; d++) x.pl[d] = ((k - {zm} + d) % {nplanes}) * {plane};")
+    w(f"      {k.name}_body(x);")
+    w("    }")
+    if cached:
+        w("    if (more) {")
+        w(f"      __syncthreads();  // every read of plane k - {zm} is done")
+        w(f"      const int sl = (kn % {nplanes}) * {plane};")
+        w(f"#pragma unroll")
+        w(f"      for (int r = 0; r < {per}; r++)")
+        w("        if (qv[r]) {")
+        for n, v in cached:
+            w(f"          s_{n}[sl + tid + r * {nthr}] = pre_{n}[r];")
+        w("        }")
+        w("      __syncthreads();")
+        w("    }")
+    w("  }")
+    w("}")
+    w("")
+
+
+def _block_kernel(k, w, tparams, targs, args, cached, lx, ly, lz):
+    tx, ty, tz = k.tile
+    xm, xp, ym, yp, zm, zp = k.stencil
     w(f"// One {tx} x {ty} x {tz} tile of {k.name} per workgroup ({tx} x {ty} threads).")
     w(f"template <{tparams}>")
     w(f"__global__ void __launch_bounds__({tx * ty})")
@@ -375,18 +506,7 @@ def generate(k: Kernel) -> str:
             w(f"    s_{n}[t] = {src}[q];")
         w("  }")
         w("  __syncthreads();")
-    w(f"  {k.name}_ctx<{targs}> x{{g}};")
-    for n, v in k.all_vars():
-        if v.cached:
-            w(f"  x.s_{n} = s_{n};")
-        if v.intent in ("IN", "OUT", "INOUT"):
-            w(f"  x.{n}_p = {n};")
-        else:
-            w(f"  x.{n}_in_p = {n}_in;")
-            w(f"  x.{n}_out_p = {n}_out;")
-    for p in k.parameters:
-        for n in p.names:
-            w(f"  x.{n} = {'ctl->' + n if p.control else n};")
+    _set_ctx(k, w, targs)
     w("  x.i = i0 + (int)threadIdx.x;")
     w("  x.j = j0 + (int)threadIdx.y;")
     w("  if (x.i > g.nx || x.j > g.ny) return;")
@@ -399,7 +519,10 @@ def generate(k: Kernel) -> str:
     w("  }")
     w("}")
     w("")
-    # launcher
+
+
+def _launcher(k, w, vals, opt):
+    tx, ty, tz = k.tile
     largs = []
     for n, v in k.all_vars():
         st = _storage(v)
@@ -438,7 +561,6 @@ def generate(k: Kernel) -> str:
     w("}  // namespace gen")
     w("}  // namespace ns")
     w("")
-    return "\n".join(L)
 
 
 def build(descriptor: str, out_dir: str) -> list:

@@ -137,10 +137,9 @@ def test_noalloc_step_validates_before_any_device_call():
 
 
 def test_advective_form_refuses_unsupported_combinations():
-    """NS_ADVECTIVE: one instance, not with the generated kernels, not with
-    recording for the adjoint (host-side validation)."""
+    """NS_ADVECTIVE: one instance, not with recording for the adjoint
+    (host-side validation)."""
     prm = dict(W.cavity(8), convection="advective")
-    assert _create(prm, flags=abi.NS_GENERATED)[0] == abi.NS_E_INVALID
     assert _create(dict(prm, checkpoint_every=2))[0] == abi.NS_E_INVALID
     arr = (abi.ns_params * 2)(make_params(prm), make_params(prm))
     h = ctypes.c_void_p()
