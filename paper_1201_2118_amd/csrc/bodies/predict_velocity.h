@@ -2,7 +2,7 @@
 // kernel: the momentum predictor F, G, H (explicit Euler step of viscous,
 // convective and body-force terms; conservative fluxes with the donor-cell
 // blend gamma), u, v, w cached with a one-cell halo.  The same expressions,
-// in the same order, as the hand-written predictor: all three components
+// in the same order, as the predictor cells of cells.h: all three components
 // are formed at every cell and stored where they are unknowns.
 #pragma once
 
@@ -20,7 +20,7 @@ __device__ __forceinline__ double body_force(const K& x, double gc, int c) {
 
 template <class K>
 __device__ __forceinline__ void PREDICT_VELOCITY_body(const K& x) {
-#pragma clang fp contract(on)  // as in the hand-written predictor
+#pragma clang fp contract(on)  // as in the predictor cells of cells.h
   const Geo& g = x.g;
   const double dt = x.dt, nu = x.nu, gamma = x.gamma;
   double Fv, Gv, Hv;

@@ -1,7 +1,9 @@
 // generated.h -- launchers of the predictor and projection generated from
-// the kernel descriptors (generated.hip); a handle created with
-// NS_GENERATED runs them in place of the hand-written kernels.  Same
-// arguments and results as launch_fgh / launch_project.
+// the kernel descriptors (generated.hip).  launch_gen_fgh is the predictor
+// of every single-domain step in the conservative form (its values equal
+// the hand-written predictor cells of cells.h bit for bit);
+// launch_gen_project replaces launch_project (same arguments and results)
+// on a handle created with NS_GENERATED.
 #pragma once
 
 #include "ns_internal.h"

@@ -1,8 +1,9 @@
 // generated.hip -- launchers of the kernels generated at build time from the
 // kernel descriptors (descriptors/kernels.ccl -> gen_<name>.h, with the
-// hand-written bodies in bodies/): the predictor (PREDICT_VELOCITY) and the
-// projection (UPDATE_VELOCITY).  A handle created with NS_GENERATED runs
-// them in place of the hand-written predictor and projection.
+// hand-written bodies in bodies/): the predictor (PREDICT_VELOCITY, the
+// predictor of every single-domain step in the conservative form) and the
+// projection (UPDATE_VELOCITY, run in place of the hand-written one by a
+// handle created with NS_GENERATED).
 #include <hip/hip_runtime.h>
 
 #include "cells.h"
