@@ -327,12 +327,70 @@ __device__ __forceinline__ double team_total(const double* part, int size, doubl
   return r;
 }
 
+// Sums of a and b over the workgroup, each in the order block_sum takes (the
+// same results bit for bit) but with one pair of barriers for both; valid in
+// thread 0.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh /* >= 32 */) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  const int t = flat_tid();
+  const int lane = t & 63, wid = t >> 6, nw = flat_size() >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[wid] = a;
+    sh[16 + wid] = b;
+  }
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+  if (wid == 0) {
+    a = lane < nw ? sh[lane] : 0.0;
+    b = lane < nw ? sh[16 + lane] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_down(a, o, 64);
+      b += __shfl_down(b, o, 64);
+    }
+  }
+}
+
+// The team's totals of two partial arrays (pa, pb: one entry per team
+// workgroup), broadcast to every thread.  A team of at most 64 workgroups
+// is summed by wave 0 alone with the shuffle tree team_total's reduction
+// applies to the same values (the other waves only add zeros there), so the
+// totals equal team_total's bit for bit with one barrier; larger teams take
+// team_total.
+__device__ __forceinline__ void team_total2(const double* pa, const double* pb, int size, double* sh, double* bc,
+                                            double& ta, double& tb) {
+  if (size > 64) {
+    ta = team_total(pa, size, sh, bc);
+    tb = team_total(pb, size, sh, bc);
+    return;
+  }
+  const int t = flat_tid();
+  if (t < 64) {
+    double a = t < size ? 0.0 + pa[t] : 0.0;
+    double b = t < size ? 0.0 + pb[t] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_down(a, o, 64);
+      b += __shfl_down(b, o, 64);
+    }
+    if (t == 0) {
+      bc[0] = a;
+      bc[1] = b;
+    }
+  }
+  __syncthreads();
+  ta = bc[0];
+  tb = bc[1];
+}
+
 struct Shared {
   Ctl lc;          // this workgroup's copy of the domain's control block
-  double sh[16];
+  double sh[32];
   double bc[2];
   int flag;
-  int dec[2];
 };
 
 // T = float: FP32 fields and sweeps inside the FP64 defect correction;
@@ -441,26 +499,30 @@ __device__ __forceinline__ void persist_body(const PItem* __restrict__ items, co
           const int ns = ns_max == 2 && m + 2 <= budget ? 2 : 1;
           double a1 = 0.0, a2 = 0.0;
           team_pass_any<float>(it, g, t, ns, m == 0, e[cur], e[cur ^ 1], r, 1, (float*)E, a1, a2);
-          const double s1 = block_sum(a1, S.sh);
-          const double s2 = block_sum(a2, S.sh);
+          block_sum2(a1, a2, S.sh);
           double* part = next_part();
           if (flat_tid() == 0) {
-            part[t.rank] = s1;
-            part[ts + t.rank] = s2;
+            part[t.rank] = a1;
+            part[ts + t.rank] = a2;
           }
           if (!team_sync(t, fl)) return;
-          const double t1 = team_total(part, ts, S.sh, S.bc);
-          const double t2 = team_total(part + ts, ts, S.sh, S.bc);
-          if (flat_tid() == 0) {
-            int stop = 0, fin = 0;
+          double t1, t2;
+          team_total2(part, part + ts, ts, S.sh, S.bc, t1, t2);
+          // every thread takes the decision from the same totals; thread 0
+          // keeps the control-block copy
+          int stop = 0, fin = 0;
+          {
+            const double thr = S.lc.thr_in;
             auto check = [&](int mm, double tot) {
               const double res = sqrt(tot / (double)n);
-              S.lc.res_in = res;
               const bool ok = isfinite(res);
-              if (!(res > S.lc.thr_in) || mm >= budget || !ok) {
+              if (flat_tid() == 0) {
+                S.lc.res_in = res;
+                if (!ok) S.lc.nonfinite = 1;
+              }
+              if (!(res > thr) || mm >= budget || !ok) {
                 stop = 1;
                 fin = mm;
-                if (!ok) S.lc.nonfinite = 1;
               }
             };
             if (m >= 1) check(m, t1);
@@ -469,11 +531,9 @@ __device__ __forceinline__ void persist_body(const PItem* __restrict__ items, co
               stop = 1;
               fin = budget;
             }
-            S.dec[0] = stop;
-            S.dec[1] = fin;
           }
-          __syncthreads();
-          const int stop = uni(S.dec[0]), fin = uni(S.dec[1]);
+          stop = uni(stop);
+          fin = uni(fin);
           if (!stop) {
             m += ns;
             cur ^= 1;
@@ -519,35 +579,35 @@ __device__ __forceinline__ void persist_body(const PItem* __restrict__ items, co
           double a1 = 0.0, a2 = 0.0;
           if (ns > 0) team_pass_any<double>(it, g, t, ns, false, P[cur], P[cur ^ 1], rd, 1, (double*)E, a1, a2);
           else team_pass_any<double>(it, g, t, 1, false, P[cur], P[cur ^ 1], rd, 0, (double*)E, a1, a2);
-          const double s1 = block_sum(a1, S.sh);
-          const double s2 = block_sum(a2, S.sh);
+          block_sum2(a1, a2, S.sh);
           double* part = next_part();
           if (flat_tid() == 0) {
-            part[t.rank] = s1;
-            part[ts + t.rank] = s2;
+            part[t.rank] = a1;
+            part[ts + t.rank] = a2;
           }
           if (!team_sync(t, fl)) return;
-          const double t1 = team_total(part, ts, S.sh, S.bc);
-          const double t2 = team_total(part + ts, ts, S.sh, S.bc);
-          if (flat_tid() == 0) {
-            int stop = 0, fin = 0;
+          double t1, t2;
+          team_total2(part, part + ts, ts, S.sh, S.bc, t1, t2);
+          int stop = 0, fin = 0;
+          {
+            const double thr = S.lc.thr;
             auto check = [&](int mm, double tot) {
               const double res = sqrt(tot / (double)n);
-              S.lc.res = res;
               const bool ok = isfinite(res);
-              if (!(res > S.lc.thr) || mm >= itermax || !ok) {
+              if (flat_tid() == 0) {
+                S.lc.res = res;
+                if (!ok) S.lc.nonfinite = 1;
+              }
+              if (!(res > thr) || mm >= itermax || !ok) {
                 stop = 1;
                 fin = mm;
-                if (!ok) S.lc.nonfinite = 1;
               }
             };
             if (m >= 1 || itermax == 0) check(m, t1);
             if (!stop && ns == 2) check(m + 1, t2);
-            S.dec[0] = stop;
-            S.dec[1] = fin;
           }
-          __syncthreads();
-          const int stop = uni(S.dec[0]), fin = uni(S.dec[1]);
+          stop = uni(stop);
+          fin = uni(fin);
           if (!stop) {
             m += ns;
             cur ^= 1;
@@ -564,6 +624,7 @@ __device__ __forceinline__ void persist_body(const PItem* __restrict__ items, co
           break;
         }
       }
+      __syncthreads();  // thread 0's control-block writes of the stop decision
       sweeps = f;
       pc = fb;
     }
