@@ -83,3 +83,34 @@ def test_steady_cavity_re100_matches_oracle():
     assert np.abs(uc - uco).max() <= 1e-12 * np.abs(uco).max()
     assert np.abs(wc - wco).max() <= 1e-12 * np.abs(wco).max()
     print(f"{n}^3 steady cavity vs oracle: {errs}", flush=True)
+
+
+def test_steady_cavity_re100_32_matches_oracle_golden():
+    """The 32^3 cavity to t = 20 against the oracle's run of the same 4000
+    steps (tests/golden/steady_32.npz, written by make_steady_32.py, which
+    calls only the oracle): equal sweep counts, every unknown and both
+    centreline profiles to 1e-12."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "steady_32.npz")
+    gold = np.load(path)
+    n, dt = 32, 0.005
+    prm = W.cavity(n, re=100.0, dt=dt, tol=1e-8, itermax=500)
+    nsteps = int(gold["steps"])
+    s = U.gpu_run(prm, nsteps)
+    st = s.stats()
+    print(f"32^3 steady cavity: GPU {st['sweeps_total']} sweeps, oracle {int(gold['sweeps_total'])}", flush=True)
+    assert st["steps"] == nsteps and abs(st["t"] - float(gold["t"])) < 1e-12
+    assert st["sweeps_total"] == int(gold["sweeps_total"])
+    m = U.masks(prm)
+    ref = [gold[f] for f in "uvw"]
+    sc = U.velocity_scale(ref, prm)
+    for c, f in enumerate("uvw"):
+        assert U.vel_rel(s.get_np(f), ref[c], m[c], sc) <= 1e-12, f
+        assert U.own_rel(s.get_np(f), ref[c], m[c], sc) <= 1e-10, f
+    assert U.pressure_rel(s.get_np("p"), gold["p"], m[3]) <= 1e-12
+    h = n // 2
+    u, w = s.get_np("u"), s.get_np("w")
+    uc = 0.5 * (u[1:n + 1, h, h] + u[1:n + 1, h + 1, h])
+    wc = 0.5 * (w[h, h, 1:n + 1] + w[h, h + 1, 1:n + 1])
+    assert np.abs(uc - gold["u_centre"]).max() <= 1e-12 * np.abs(gold["u_centre"]).max()
+    assert np.abs(wc - gold["w_centre"]).max() <= 1e-12 * np.abs(gold["w_centre"]).max()
