@@ -261,13 +261,26 @@ ns_status validate(const ns_params& p, int idx) {
   return NS_OK;
 }
 
+// The fused one-sweep kernels address a plane with 32-bit byte offsets:
+// planes must stay under 2^31 bytes (the two-sweep pass has the same limit,
+// pass_grid_ok).  Larger planes take the unfused sweeps.
+bool fused_grid_ok(const Geo& g, size_t esz) { return (double)g.sxy * (double)esz < 2147483648.0; }
+
+// Whether a sweep shape may run on a grid: fused shapes need fused_grid_ok,
+// pass shapes pass_grid_ok and their row count; the unfused sweeps run on
+// every grid.
+bool shape_fits_grid(const SorShape& sh, const Geo& g, size_t esz) {
+  if (sh.ty < 0) return true;
+  if (sh.ty == 4 || sh.ty == 8 || sh.ty == 12) return fused_grid_ok(g, esz);
+  return pass_grid_ok(g, esz) && pass_rows_ok(sh.ty, esz == 4);
+}
+
 // Sweep shape: the caller's tile descriptor, or a size-based default that
 // the autotuner may replace (see autotune()).
 SorShape pick_shape(const ns_params& p, const Geo& g, size_t esz) {
   if (p.tile[0] < 0) return SorShape{-1, 0};
   if (p.tile[0] > 0) return SorShape{p.tile[0], p.tile[1]};
-  // the fused kernels address a plane with 32-bit byte offsets
-  if ((double)g.sxy * (double)esz >= 2147483648.0) return SorShape{-1, 0};
+  if (!fused_grid_ok(g, esz)) return SorShape{-1, 0};
   const long n = (long)g.nx * g.ny * g.nz;
   if (n >= (1L << 24)) return SorShape{8, 128};
   return SorShape{8, 0};
@@ -402,7 +415,9 @@ ns_status tune_run(ns_solver* s, Inst& I, Ctl* tctl, const SorShape& sh, float* 
 
 ns_status autotune(ns_solver* s, Inst& I) {
   const long n = (long)I.g.nx * I.g.ny * I.g.nz;
-  if (I.prm.tile[0] != 0 || n < (1L << 21)) return NS_OK;
+  // planes too large for the fused kernels are too large for the pass too:
+  // the unfused sweeps are the only shape
+  if (I.prm.tile[0] != 0 || n < (1L << 21) || !fused_grid_ok(I.g, I.esz)) return NS_OK;
   const TuneKey key{I.g.nx, I.g.ny, I.g.nz, (int)I.esz, I.g.per[0] | (I.g.per[1] << 1) | (I.g.per[2] << 2)};
   const std::string tag = tune_device_tag(s->device);
   {
@@ -412,7 +427,7 @@ ns_status autotune(ns_solver* s, Inst& I) {
       g_tune_loaded = true;
     }
     for (auto& kv : g_tune_cache)
-      if (kv.first == key) { I.shape = kv.second; return NS_OK; }
+      if (kv.first == key && shape_fits_grid(kv.second, I.g, I.esz)) { I.shape = kv.second; return NS_OK; }
   }
   Ctl* tctl = nullptr;
   HCK(s, dmalloc((void**)&tctl, sizeof(Ctl)));
@@ -1887,7 +1902,8 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
   // several instances of one precision: one launch per sweep for all of them
   {
     bool same = n_instances > 1;
-    for (auto& I : s->in) same &= I.mixed == s->in[0].mixed && I.prm.tile[0] >= 0;
+    // (the batched sweeps are fused or pass tiles: every plane within their offsets)
+    for (auto& I : s->in) same &= I.mixed == s->in[0].mixed && I.prm.tile[0] >= 0 && fused_grid_ok(I.g, I.esz);
     s->batched = same;
   }
   if (s->batched) {
