@@ -323,6 +323,8 @@ def main():
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="after the runs, copy this many GiB device-to-device once (a plain copy of "
                          "known size that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--no-slab", action="store_true",
+                    help="skip the one-GPU share of an 8-way z-slab split (512 x 512 x 64, mixed)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched workload (--batched-steps steps) and print its figures "
                          "as one JSON line (for profiling it alone)")
@@ -428,6 +430,20 @@ def main():
         r["final"] = None
     import torch
     torch.cuda.empty_cache()
+    if not args.no_slab and args.n % 8 == 0:
+        # one GPU's share if the cavity were split into 8 z slabs: the same
+        # kernels on n x n x n/8 cells (walls at the slab ends stand in for
+        # the ghost planes a neighbour would send)
+        sl = dict(prm, nz=args.n // 8, lz=prm["lz"] / 8, precision="mixed")
+        r = measure(sl, args.steps, args.warmup)
+        out["slab_share"] = {"grid": [args.n, args.n, args.n // 8], "precision": "mixed",
+                             "value": round(r["mcells"], 2), "unit": "Mcell-steps/s",
+                             "ms_per_step": round(r["ms_per_step"], 3), "sor_avg_ms": round(r["sor_avg_ms"], 5),
+                             "sor_launches_per_step": r["sor_launches_per_step"], "tile": r["tile"],
+                             "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()}}
+        log(f"slab share {args.n}x{args.n}x{args.n // 8}: {r['mcells']:.1f} Mcell-steps/s, "
+            f"sor {r['sor_avg_ms'] * 1e3:.1f} us/launch")
+        torch.cuda.empty_cache()
     if args.batched_steps > 0:
         out["batched"] = measure_batched(args.batched_steps)
         log(f"batched: {out['batched']['value']} Mcell-steps/s over {out['batched']['instances']} cavities")
