@@ -231,6 +231,32 @@ def test_batched_workload_runs():
     print(f"64 cavities, 2 steps: worst velocity difference to the standalone runs {worst:.2e}", flush=True)
 
 
+@pytest.mark.parametrize("tile", [(24, 0), (32, 0)])
+def test_batched_workload_pass_tiles_match_standalone(tile):
+    """The 64-cavity workload in the multi-launch form with explicit FP32
+    24- and 32-row two-sweep tiles (the batched pass kernel): every instance
+    takes the same sweeps as its standalone run with the same tile and
+    matches its velocity to 1e-6 of its scale."""
+    prms, _ = W.batched_64()
+    prms = [dict(p, precision="mixed", tile=tile) for p in prms]
+    from paper_1201_2118_amd.solver import Solver
+    s = Solver(prms)
+    s.step(2)
+    assert list(s.timing().sor_tile) == list(tile)
+    for i, prm in enumerate(prms):
+        st = s.stats(i)
+        one = U.gpu_run(prm, 2)
+        assert st["sweeps_total"] == one.stats()["sweeps_total"], (i, st, one.stats())
+        assert st["t"] == one.stats()["t"], i
+        m = U.masks(prm)
+        ref = [one.get_np(f) for f in "uvw"]
+        sc = U.velocity_scale(ref, prm)
+        for c, f in enumerate("uvw"):
+            assert U.vel_rel(s.get_np(f, i), ref[c], m[c], sc) < 1e-6, (i, f)
+        one.close()
+    s.close()
+
+
 def test_nonfinite_state_is_reported():
     from paper_1201_2118_amd import abi
     prm = W.cavity(10)
