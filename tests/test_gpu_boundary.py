@@ -42,7 +42,7 @@ def test_nsrollout_autograd_matches_oracle_gradient():
     u, v, w = NSRollout.apply(x[0], x[1], x[2], prm, steps)
     loss = 0.5 * sum(torch.sum(torch.where(m, q - t, torch.zeros_like(q)) ** 2)
                      for q, t, m in zip((u, v, w), tg, masks))
-    assert abs(float(loss) - loss_o) <= 1e-10 * abs(loss_o)
+    assert abs(loss.detach().item() - loss_o) <= 1e-10 * abs(loss_o)
     gx = torch.autograd.grad(loss, x)
     for c in range(3):
         g = gx[c].cpu().numpy()
