@@ -66,14 +66,21 @@ def test_adjoint_64_central_differences_16_directions():
     from paper_1201_2118_amd.solver import Solver
     fwd = dict(prm, checkpoint_every=0)
 
-    def loss(x):
-        s = Solver(fwd)
-        for f, a in zip("uvw", x):
-            s.set(f, a)
+    def losses(xs):
+        # every perturbed run in one batched handle (one persistent launch per
+        # call; each domain keeps its own stop rule and equals its standalone
+        # run to rounding)
+        s = Solver([fwd] * len(xs))
+        for i, x in enumerate(xs):
+            for f, a in zip("uvw", x):
+                s.set(f, a, i)
         s.step(nsteps)
-        r = [np.where(mk[c], s.get_np(f) - tgt[c], 0.0) for c, f in enumerate("uvw")]
+        out = []
+        for i in range(len(xs)):
+            r = [np.where(mk[c], s.get_np(f, i) - tgt[c], 0.0) for c, f in enumerate("uvw")]
+            out.append(0.5 * sum(float(np.sum(a * a)) for a in r))
         s.close()
-        return 0.5 * sum(float(np.sum(a * a)) for a in r)
+        return out
 
     s = U.gpu_run(prm, nsteps, {"u": u0[0], "v": u0[1], "w": u0[2]})
     gf = [np.where(mk[c], s.get_np(f) - tgt[c], 0.0) for c, f in enumerate("uvw")]
@@ -84,12 +91,18 @@ def test_adjoint_64_central_differences_16_directions():
     # tiny derivative whose finite difference sits at the noise floor of the
     # 1e-12 solves (about 1e-9 absolute here).
     gnorm = np.sqrt(sum(float(np.sum(g * g)) for g in grad))
-    worst = 0.0
-    for k, d in enumerate(W.directions(prm, 16, 7)):
+    dirs = []
+    for d in W.directions(prm, 16, 7):
         d = [np.where(mk[c], x, 0.0) for c, x in enumerate(d)]
         nrm = np.sqrt(sum(float(np.sum(x * x)) for x in d))
-        d = [x / nrm for x in d]
-        fd = (loss([a + eps * b for a, b in zip(u0, d)]) - loss([a - eps * b for a, b in zip(u0, d)])) / (2 * eps)
+        dirs.append([x / nrm for x in d])
+    xs = []
+    for d in dirs:
+        xs += [[a + eps * b for a, b in zip(u0, d)], [a - eps * b for a, b in zip(u0, d)]]
+    L = losses(xs)
+    worst = 0.0
+    for k, d in enumerate(dirs):
+        fd = (L[2 * k] - L[2 * k + 1]) / (2 * eps)
         an = sum(float(np.sum(g * x)) for g, x in zip(grad, d))
         err = abs(fd - an) / gnorm
         worst = max(worst, err)
