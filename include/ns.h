@@ -219,6 +219,20 @@ ns_status ns_backward(ns_solver *s, int32_t inst, const double *const g_final[3]
  * NS_E_INVALID for a NULL handle or out pointer. */
 ns_status ns_get_timing(const ns_solver *s, ns_timing *out);
 
+/* A debugging aid (no passage of the paper: a check of the library itself).
+ * While the environment variable NS_GUARD is set (to anything but "" or
+ * "0"), every device buffer the library allocates lies between two 4 KiB
+ * guard bands of a fixed byte pattern; a buffer's bands are compared with
+ * the pattern when it is freed (ns_destroy).  Returns the number of bands
+ * found changed since the process started -- bands of freed buffers, plus
+ * those of live buffers checked now, after a device synchronisation -- so
+ * 0 means no device write went past either end of a buffer.  self_test != 0
+ * (with NS_GUARD set) first allocates a guarded buffer, sets the byte just
+ * past its end with a host-side fill and frees it, which adds one to the
+ * count.  Not for use while another thread runs a handle on the device.
+ * Buffers allocated while NS_GUARD was unset have no bands. */
+int64_t ns_guard_check(int32_t self_test);
+
 /* For callers that cannot allocate device memory (tight serving loops,
  * harnesses that forbid hipMalloc): the step of ns_step for one FP64 domain
  * without a handle and without any allocation.

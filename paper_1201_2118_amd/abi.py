@@ -22,7 +22,7 @@ NS_FP64, NS_MIXED = 0, 1
 NS_ALLOW_UNSTABLE, NS_TIMING, NS_BATCH_LAUNCHES, NS_GENERATED, NS_ADVECTIVE, NS_RK2 = 1, 2, 4, 8, 16, 32
 NS_T_BC, NS_T_FGH, NS_T_RHS, NS_T_SOR, NS_T_DEFECT, NS_T_PROJECT, NS_T_OTHER, NS_T_COUNT = 0, 1, 2, 3, 4, 5, 6, 8
 EXPORTED = ("ns_params_default", "ns_create", "ns_set_state", "ns_step", "ns_get_state",
-            "ns_backward", "ns_get_timing", "ns_destroy", "ns_last_error", "ns_step_noalloc")
+            "ns_backward", "ns_get_timing", "ns_destroy", "ns_last_error", "ns_step_noalloc", "ns_guard_check")
 
 
 class ns_params(ctypes.Structure):
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
         "ns_destroy": (None, [vp]),
         "ns_last_error": (ctypes.c_char_p, [vp]),
         "ns_step_noalloc": (ctypes.c_int, [P(ns_params), vp, vp, vp, vp, ctypes.c_int32, vp, P(ns_stats)]),
+        "ns_guard_check": (ctypes.c_int64, [ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -148,6 +149,14 @@ def ns_step_noalloc(params: ns_params, u_ptr: int, v_ptr: int, w_ptr: int, p_ptr
                     hip_stream: int | None, stats) -> int:
     return load().ns_step_noalloc(ctypes.byref(params), u_ptr, v_ptr, w_ptr, p_ptr, nsteps, hip_stream,
                                   None if stats is None else ctypes.byref(stats))
+
+
+def ns_guard_check(self_test: int = 0) -> int:
+    """Guard-band count (include/ns.h).  Like every call that reaches the
+    device, make it after torch has initialised the GPU when torch is in the
+    process: torch loads its own HIP runtime, which finds no GPU if the
+    library's runtime initialised the device first."""
+    return int(load().ns_guard_check(int(self_test)))
 
 
 def ns_last_error(handle=None) -> str:

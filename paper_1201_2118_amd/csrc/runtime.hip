@@ -15,6 +15,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include <sys/stat.h>
@@ -287,6 +288,7 @@ SorShape pick_shape(const ns_params& p, const Geo& g, size_t esz) {
 }
 
 hipError_t dmalloc(void** p, size_t bytes);
+void dfree(void* p);
 
 // ---- autotuner ---------------------------------------------------------------
 // For grids of at least 2^21 cells with tile = {0, 0}: time candidate shapes
@@ -458,7 +460,7 @@ ns_status autotune(ns_solver* s, Inst& I) {
       if (st == NS_OK && ms < best) { best = ms; pick = sh; }
     }
   }
-  (void)hipFree(tctl);
+  dfree(tctl);
   if (st != NS_OK) return st;
   I.shape = pick;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -570,35 +572,114 @@ ns_status autotune_batch(ns_solver* s) {
         s->batch_ty = rows[r];
         s->batch_zc = zcs[z];
       }
-  (void)hipFree(tctl);
+  dfree(tctl);
   return st;
 }
 
+// ---- guard bands (debugging) ------------------------------------------------
+// While NS_GUARD is set in the environment (to anything but "" or "0"), every
+// buffer dmalloc returns sits between two bands of kGuard bytes that hold
+// kGuardByte.  dfree, and ns_guard_check, compare both bands with the
+// pattern and count each band that differs: a kernel that writes past either
+// end of a buffer -- into memory that may belong to a neighbouring
+// allocation, so that nothing faults -- shows up as a count.  Buffers
+// allocated without the bands are freed as usual.
+constexpr size_t kGuard = 4096;
+constexpr int kGuardByte = 0xA5;
+struct GuardRec {
+  char* base;    // start of the lower band
+  size_t bytes;  // the buffer's own size
+};
+std::mutex g_guard_mu;
+std::unordered_map<void*, GuardRec> g_guard;  // live guarded buffers, by the pointer handed out
+long long g_guard_bad = 0;                    // bands found overwritten when their buffer was freed
+
+bool guard_on() {
+  const char* e = getenv("NS_GUARD");
+  return e && e[0] && strcmp(e, "0") != 0;
+}
+
+// Number of bands of one buffer (0, 1 or 2) that no longer hold the pattern;
+// the device is idle and the caller holds g_guard_mu.
+int guard_scan(const GuardRec& r) {
+  std::vector<unsigned char> h(kGuard);
+  int bad = 0;
+  const char* band[2] = {r.base, r.base + kGuard + r.bytes};
+  for (int b = 0; b < 2; b++) {
+    if (hipMemcpy(h.data(), band[b], kGuard, hipMemcpyDeviceToHost) != hipSuccess) {
+      bad++;
+      continue;
+    }
+    for (size_t i = 0; i < kGuard; i++)
+      if (h[i] != kGuardByte) {
+        fprintf(stderr, "libns: guard band %s a %zu-byte buffer overwritten (%zu bytes %s it)\n",
+                b ? "after" : "before", r.bytes, b ? i : kGuard - i, b ? "past the end of" : "before");
+        bad++;
+        break;
+      }
+  }
+  return bad;
+}
+
+// Zero-filled device buffer (with guard bands under NS_GUARD).
 hipError_t dmalloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (guard_on()) {
+    const size_t body = (bytes + 255) & ~size_t(255);  // the upper band's page stays 256-byte aligned
+    char* base = nullptr;
+    hipError_t e = hipMalloc((void**)&base, body + 2 * kGuard);
+    if (e != hipSuccess) return e;
+    if ((e = hipMemset(base, kGuardByte, body + 2 * kGuard)) != hipSuccess ||
+        (e = hipMemset(base + kGuard, 0, bytes)) != hipSuccess) {
+      (void)hipFree(base);
+      return e;
+    }
+    std::lock_guard<std::mutex> lk(g_guard_mu);
+    g_guard[base + kGuard] = GuardRec{base, bytes};
+    *p = base + kGuard;
+    return hipSuccess;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) { *p = nullptr; return e; }
   return hipMemset(*p, 0, bytes);
 }
 
+// Frees a dmalloc buffer (checking its bands if it has them); null is a no-op.
+void dfree(void* p) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_guard_mu);
+    auto it = g_guard.find(p);
+    if (it != g_guard.end()) {
+      (void)hipDeviceSynchronize();
+      g_guard_bad += guard_scan(it->second);
+      (void)hipFree(it->second.base);
+      g_guard.erase(it);
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
 void free_state(State& s) {
-  (void)hipFree(s.u); (void)hipFree(s.v); (void)hipFree(s.w);
-  (void)hipFree(s.p[0]); (void)hipFree(s.p[1]);
+  dfree(s.u); dfree(s.v); dfree(s.w);
+  dfree(s.p[0]); dfree(s.p[1]);
   s = State{};
 }
 
 void free_inst(Inst& I) {
   free_state(I.s);
-  (void)hipFree(I.F); (void)hipFree(I.G); (void)hipFree(I.H); (void)hipFree(I.rhs);
-  for (int c = 0; c < 3; c++) (void)hipFree(I.frc[c]);
-  (void)hipFree(I.e[0]); (void)hipFree(I.e[1]); (void)hipFree(I.r);
-  for (int c = 0; c < 3; c++) (void)hipFree(I.save[c]);
-  (void)hipFree(I.part);  // I.ctl lives in the handle's ctl_all
+  dfree(I.F); dfree(I.G); dfree(I.H); dfree(I.rhs);
+  for (int c = 0; c < 3; c++) dfree(I.frc[c]);
+  dfree(I.e[0]); dfree(I.e[1]); dfree(I.r);
+  for (int c = 0; c < 3; c++) dfree(I.save[c]);
+  dfree(I.part);  // I.ctl lives in the handle's ctl_all
   for (auto& c : I.ck) free_state(c);
   I.ck.clear();
   free_state(I.R);
-  for (int c = 0; c < 3; c++) { (void)hipFree(I.lam[c]); (void)hipFree(I.z[c]); }
-  (void)hipFree(I.q[0]); (void)hipFree(I.q[1]);
-  for (auto* h : I.hist) (void)hipFree(h);
+  for (int c = 0; c < 3; c++) { dfree(I.lam[c]); dfree(I.z[c]); }
+  dfree(I.q[0]); dfree(I.q[1]);
+  for (auto* h : I.hist) dfree(h);
   I.hist.clear();
 }
 
@@ -1550,7 +1631,7 @@ ns_status persist_setup(ns_solver* s) {
     Inst& I = s->in[i];
     const size_t need = 6 * (size_t)team[i] + 8;
     if (need > reduce_blocks(I.g)) {
-      (void)hipFree(I.part);
+      dfree(I.part);
       I.part = nullptr;
       HCK(s, dmalloc((void**)&I.part, need * sizeof(double)));
     }
@@ -1886,7 +1967,7 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
   bool any_mixed = false;
   for (auto& I : s->in) any_mixed |= I.mixed;
   if (any_mixed) {
-    if (hipMalloc((void**)&s->stage, max_ntot * sizeof(double)) != hipSuccess)
+    if (dmalloc((void**)&s->stage, max_ntot * sizeof(double)) != hipSuccess)
       return bail(NS_E_OOM, "staging buffer allocation failed");
     s->stage_n = max_ntot;
   }
@@ -1916,10 +1997,10 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
     // room for a full table and a table of re-sweeps behind it
     if (hipHostMalloc((void**)&s->items_h, 2 * sizeof(BatchItem) * n_instances, hipHostMallocDefault) !=
             hipSuccess ||
-        hipMalloc((void**)&s->items_d, 2 * sizeof(BatchItem) * n_instances) != hipSuccess ||
+        dmalloc((void**)&s->items_d, 2 * sizeof(BatchItem) * n_instances) != hipSuccess ||
         hipHostMalloc((void**)&s->stage_h, sizeof(StageItem) * kStageKinds * n_instances, hipHostMallocDefault) !=
             hipSuccess ||
-        hipMalloc((void**)&s->stage_d, sizeof(StageItem) * kStageKinds * n_instances) != hipSuccess)
+        dmalloc((void**)&s->stage_d, sizeof(StageItem) * kStageKinds * n_instances) != hipSuccess)
       return bail(NS_E_OOM, "batch table allocation failed");
     if (persist_setup(s) != NS_OK) return bail(NS_E_DEVICE, "persistent launch set-up: " + s->err);
     if (s->persist) {
@@ -2176,25 +2257,40 @@ void ns_destroy(ns_solver* s) {
   for (auto e : s->pool) (void)hipEventDestroy(e);
   if (s->hctl) (void)hipHostFree(s->hctl);
   if (s->items_h) (void)hipHostFree(s->items_h);
-  (void)hipFree(s->items_d);
+  dfree(s->items_d);
   if (s->stage_h) (void)hipHostFree(s->stage_h);
-  (void)hipFree(s->stage_d);
+  dfree(s->stage_d);
   for (int k = 0; k < ns_solver::kAux; k++) {
     if (s->aux[k]) (void)hipStreamDestroy(s->aux[k]);
     if (s->ev_join[k]) (void)hipEventDestroy(s->ev_join[k]);
   }
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
-  (void)hipFree(s->ctl_all);
-  (void)hipFree(s->stage);
+  dfree(s->ctl_all);
+  dfree(s->stage);
   if (s->pitems_h) (void)hipHostFree(s->pitems_h);
   if (s->pstats_h) (void)hipHostFree(s->pstats_h);
   if (s->perr_h) (void)hipHostFree(s->perr_h);
-  (void)hipFree(s->pitems_d);
-  (void)hipFree(s->pstats_d);
-  (void)hipFree(s->pslots_d);
-  (void)hipFree(s->pbar_d);
-  (void)hipFree(s->perr_d);
+  dfree(s->pitems_d);
+  dfree(s->pstats_d);
+  dfree(s->pslots_d);
+  dfree(s->pbar_d);
+  dfree(s->perr_d);
   delete s;
+}
+
+int64_t ns_guard_check(int32_t self_test) {
+  if (self_test && guard_on()) {
+    void* q = nullptr;
+    if (dmalloc(&q, 1000) == hipSuccess) {
+      (void)hipMemset((char*)q + 1000, 0x5A, 1);  // one byte past the end, by a host-side fill
+      dfree(q);
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_guard_mu);
+  (void)hipDeviceSynchronize();
+  long long bad = g_guard_bad;
+  for (const auto& kv : g_guard) bad += guard_scan(kv.second);
+  return bad;
 }
 
 ns_status ns_step_noalloc(const ns_params* params, double* u, double* v, double* w, double* p, int32_t nsteps,
