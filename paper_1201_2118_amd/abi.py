@@ -78,6 +78,14 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         from . import build as _build
         _build.build()
+    # torch ships its own HIP runtime under the soname the library needs; when
+    # torch is installed, load it first so that the process holds one HIP
+    # runtime (with the system runtime loaded first, torch maps a second one
+    # and finds no GPU)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     P = ctypes.POINTER
@@ -152,10 +160,7 @@ def ns_step_noalloc(params: ns_params, u_ptr: int, v_ptr: int, w_ptr: int, p_ptr
 
 
 def ns_guard_check(self_test: int = 0) -> int:
-    """Guard-band count (include/ns.h).  Like every call that reaches the
-    device, make it after torch has initialised the GPU when torch is in the
-    process: torch loads its own HIP runtime, which finds no GPU if the
-    library's runtime initialised the device first."""
+    """Guard-band count (include/ns.h)."""
     return int(load().ns_guard_check(int(self_test)))
 
 
