@@ -59,6 +59,56 @@ def test_fixed_sweep_count(dims, bc, k):
 
 # ---- whole steps ----------------------------------------------------------------
 
+@pytest.mark.parametrize("tile", [(0, 0), (4, 0), (8, 3), (12, 0), (-1, 0)])
+@pytest.mark.parametrize("dims,bc", [((2, 2, 2), (1, 1, 1)), ((2, 6, 4), (1, 0, 1)), ((4, 2, 3), (1, 1, 0)),
+                                     ((5, 2, 2), (0, 1, 1))])
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_two_cell_periodic_axes(dims, bc, tile, form):
+    """Periodic axes of two cells, the shortest the library accepts: a cell's
+    two neighbours along such an axis are the same cell, and the sweep tiles'
+    two-cell halos wrap exactly once.  Three steps against the oracle, every
+    one-sweep shape (the two-sweep pass needs periodic axes of four cells)."""
+    prm = W.cavity(dims[0], ny=dims[1], nz=dims[2], re=60.0, dt=0.002, tol=1e-10, itermax=80)
+    prm.update(bc=bc, precision=form, tile=tile, lx=0.4, ly=0.5, lz=0.6)
+    prm["wall_vel"] = [[0.0] * 3 for _ in range(6)]
+    for a in range(3):
+        if not bc[a]:
+            prm["wall_vel"][2 * a + 1] = [0.8 if a != 0 else 0.0, 0.5 if a != 1 else 0.0, 0.3 if a != 2 else 0.0]
+    prm["g"] = (0.2, -0.1, 0.3)
+    init = U.random_state(prm, 31, amp=0.4)
+    s = U.gpu_run(prm, 3, init)
+    o, rc = U.oracle_run(dict(prm, precision="fp64"), 3, init, mode=1 if form == "mixed" else 0)
+    assert rc == 0
+    if form == "fp64":
+        assert s.stats()["sweeps_total"] == o.stats.sweeps_total
+        U.compare_state(s, o, prm, 1e-12)
+    else:
+        U.compare_state(s, o, prm, 1e-5, ptol=1e-4)
+
+
+@pytest.mark.parametrize("n_dom", [1, 3])
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_zero_steps_leave_state_unchanged(n_dom, form):
+    """ns_step(0) on a single and a batched (persistent) handle: no step, the
+    state and the statistics as they were."""
+    from paper_1201_2118_amd.solver import Solver
+    prms = [dict(W.cavity(12 + 2 * i, ny=10, nz=9 + i, dt=0.0, tau=0.5), precision=form) for i in range(n_dom)]
+    s = Solver(prms)
+    inits = [U.random_state(p, 60 + i, amp=0.2) for i, p in enumerate(prms)]
+    for i, init in enumerate(inits):
+        for name, arr in init.items():
+            s.set(name, arr, i)
+    s.step(1)
+    before = [{f: s.get_np(f, i) for f in "uvwp"} for i in range(n_dom)]
+    st0 = [s.stats(i) for i in range(n_dom)]
+    s.step(0)
+    for i in range(n_dom):
+        assert s.stats(i) == st0[i]
+        for f in "uvwp":
+            assert np.array_equal(s.get_np(f, i), before[i][f]), (i, f)
+    s.close()
+
+
 def test_cavity_16_ten_steps():
     """The 16^3 lid-driven cavity, Re 100, dt 0.01, gamma 0.5, omega 1.7,
     tol 1e-6, 200 sweeps, 10 steps."""
