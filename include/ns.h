@@ -43,7 +43,10 @@
  *    calls return after the copy completed.  The library owns all device
  *    memory it allocates (in ns_create, freed in ns_destroy).
  *  - ns_step is synchronous: it returns when the steps are done.
- *  - One host thread per handle at a time.
+ *  - One host thread per handle at a time.  Handles may be driven from
+ *    different threads at once (on different streams); the persistent
+ *    launches of batched handles on one device then take turns, since each
+ *    needs the whole device.
  */
 #ifndef NSMI_NS_H_
 #define NSMI_NS_H_

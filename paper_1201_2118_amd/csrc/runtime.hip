@@ -1656,7 +1656,18 @@ ns_status persist_setup(ns_solver* s) {
 }
 
 // nsteps steps of every domain in one launch.
+// Persistent launches on one device take turns (held from the first copy to
+// the final synchronisation): each grid fills every compute unit, and two
+// grids dispatched side by side by handles on different streams could each
+// hold part of the device while their team barriers wait for workgroups that
+// only the other grid's exit would let in -- until the wait limit failed both.
+std::mutex& persist_device_mutex(int device) {
+  static std::mutex mu[64];
+  return mu[device & 63];
+}
+
 ns_status persist_run(ns_solver* s, int nsteps) {
+  std::lock_guard<std::mutex> turn(persist_device_mutex(s->device));
   const int n = (int)s->in.size();
   const bool f32 = s->in[0].mixed;
   std::vector<long long> sweeps0(n);

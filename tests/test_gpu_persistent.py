@@ -116,3 +116,47 @@ def test_persistent_barrier_wait_gives_up():
     s = Solver(prms)
     s.step(1)
     assert all(s.stats(i)["steps"] == 1 for i in range(len(prms)))
+
+
+def test_two_batched_handles_step_from_two_threads():
+    """Two batched handles on their own streams, stepped from two host threads
+    at once: their persistent launches take turns and each result equals the
+    same handle stepped alone, bit for bit."""
+    import threading
+
+    import torch
+
+    from paper_1201_2118_amd.solver import Solver
+    a = [dict(W.cavity(20, ny=16, nz=12, dt=0.0, tau=0.5), precision="mixed"),
+         dict(W.cavity(14, re=300.0, dt=0.003), precision="mixed")]
+    b = [dict(W.cavity(18, ny=22, nz=10, re=200.0, dt=0.002)), dict(W.periodic_box(12, nz=8, dt=1e-3)),
+         dict(W.cavity(9, ny=11, nz=13, dt=0.0, tau=0.5))]
+    ref = {}
+    for name, prms in (("a", a), ("b", b)):
+        s = Solver(prms)
+        for _ in range(4):
+            s.step(1)
+        ref[name] = [[s.get_np(f, i) for f in "uvwp"] for i in range(len(prms))]
+        s.close()
+    hs = {"a": Solver(a, stream=torch.cuda.Stream()), "b": Solver(b, stream=torch.cuda.Stream())}
+    errs = []
+
+    def run(s):
+        try:
+            for _ in range(4):
+                s.step(1)
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    th = [threading.Thread(target=run, args=(h,)) for h in hs.values()]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in th)
+    assert not errs, errs
+    for name, s in hs.items():
+        for i in range(len(ref[name])):
+            for f, r in zip("uvwp", ref[name][i]):
+                assert np.array_equal(s.get_np(f, i), r), (name, i, f)
+        s.close()
