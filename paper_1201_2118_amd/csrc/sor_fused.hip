@@ -129,17 +129,28 @@ __device__ __forceinline__ void sweep_tile(const T* __restrict__ p_in, T* __rest
     sp[(L - 1) & 1][lid] = (T)pm1;
     lds_barrier();
 
-    // residual of the input and red update at plane k1 = L - 1
+    // residual of the input and red update at plane k1 = L - 1.  A plane with
+    // both z neighbours takes the z term in the steady-state planes' form, so
+    // a cell's value does not depend on which of the two paths (and thus on
+    // which z chunking) computed it; at a z wall the missing term is dropped.
     const int k1 = L - 1;
-    const A azm1 = (k1 > 1 || per2) ? idz2 : A(0);
-    const A azp1 = (k1 < g.nz || per2) ? idz2 : A(0);
+    const bool zin1 = (k1 > 1 && k1 < g.nz) || per2;  // uniform over the workgroup
+    const A azm1 = k1 > 1 ? idz2 : A(0);
+    const A azp1 = k1 < g.nz ? idz2 : A(0);
+    const A two = A(2);
     A rnew = pm1;
     if (halo1) {
       const T* P = sp[(L - 1) & 1];
       const A pc = pm1;
-      const A s = axm * ((A)P[lid - 1] - pc) + axp * ((A)P[lid + 1] - pc) +
-                  aym * ((A)P[lid - kW] - pc) + ayp * ((A)P[lid + kW] - pc) +
-                  azm1 * (pm2 - pc) + azp1 * (p0 - pc);
+      A s;
+      if (zin1)
+        s = axm * ((A)P[lid - 1] - pc) + axp * ((A)P[lid + 1] - pc) +
+            aym * ((A)P[lid - kW] - pc) + ayp * ((A)P[lid + kW] - pc) +
+            idz2 * (pm2 + p0 - two * pc);
+      else
+        s = axm * ((A)P[lid - 1] - pc) + axp * ((A)P[lid + 1] - pc) +
+            aym * ((A)P[lid - kW] - pc) + ayp * ((A)P[lid + kW] - pc) +
+            azm1 * (pm2 - pc) + azp1 * (p0 - pc);
       const A r = s - rh1;
       if (own && k1 >= z0 && k1 <= z1) acc += (double)r * (double)r;
       if (!((cpar + k1) & 1)) {
@@ -156,11 +167,18 @@ __device__ __forceinline__ void sweep_tile(const T* __restrict__ p_in, T* __rest
       if ((cpar + k2) & 1) {
         const T* R = sr[(L - 2) & 1];
         const A pc = pm2;
-        const A azm2 = (k2 > 1 || per2) ? idz2 : A(0);
-        const A azp2 = (k2 < g.nz || per2) ? idz2 : A(0);
-        const A s = axm * ((A)R[lid - 1] - pc) + axp * ((A)R[lid + 1] - pc) +
-                    aym * ((A)R[lid - kW] - pc) + ayp * ((A)R[lid + kW] - pc) +
-                    azm2 * (rnA - pc) + azp2 * (rnew - pc);
+        const bool zin2 = (k2 > 1 && k2 < g.nz) || per2;
+        const A azm2 = k2 > 1 ? idz2 : A(0);
+        const A azp2 = k2 < g.nz ? idz2 : A(0);
+        A s;
+        if (zin2)
+          s = axm * ((A)R[lid - 1] - pc) + axp * ((A)R[lid + 1] - pc) +
+              aym * ((A)R[lid - kW] - pc) + ayp * ((A)R[lid + kW] - pc) +
+              idz2 * (rnA + rnew - two * pc);
+        else
+          s = axm * ((A)R[lid - 1] - pc) + axp * ((A)R[lid + 1] - pc) +
+              aym * ((A)R[lid - kW] - pc) + ayp * ((A)R[lid + kW] - pc) +
+              azm2 * (rnA - pc) + azp2 * (rnew - pc);
         const A r = s - rh2;
         const A wk = (k2 > 1 && k2 < g.nz) ? w_mid : w_lo;
         out = pc + wk * r;

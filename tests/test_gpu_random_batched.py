@@ -1,7 +1,8 @@
 """Seeded random batches of uneven domains in one persistent launch (and in
 the multi-launch form) against each domain's standalone run: equal sweep
-counts and time, velocities to 1e-12 (FP64) or 1e-6 (mixed: the sweep
-shapes differ in their FP32 rounding)."""
+counts, simulated time to rounding (1e-14: adaptive steps come from velocity
+maxima, and the sweep shapes differ in rounding), velocities to 1e-12 (FP64)
+or 1e-6 (mixed: the sweep shapes differ in their FP32 rounding)."""
 import numpy as np
 import pytest
 
@@ -46,7 +47,7 @@ def test_random_batch_matches_standalone_runs(seed, launches):
         one = U.gpu_run(p, 2, inits[i])
         st, so = s.stats(i), one.stats()
         assert st["sweeps_total"] == so["sweeps_total"], (i, p, st, so)
-        assert st["t"] == so["t"], (i, p)
+        assert U.close_time(st["t"], so["t"]), (i, p)
         m = U.masks(p)
         ref = [one.get_np(f) for f in "uvw"]
         sc = U.velocity_scale(ref, p)
