@@ -157,6 +157,9 @@ ns_status fail(ns_solver* s, ns_status code, const std::string& msg) {
 }
 
 ns_status fail_hip(ns_solver* s, const char* what, hipError_t e) {
+  // the failure is reported here: clear it from the thread's last-error
+  // state, or the launch check of a later call would report it again
+  (void)hipGetLastError();
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
   return fail(s, e == hipErrorOutOfMemory ? NS_E_OOM : NS_E_DEVICE, m);
 }
@@ -628,7 +631,10 @@ hipError_t dmalloc(void** p, size_t bytes) {
     const size_t body = (bytes + 255) & ~size_t(255);  // the upper band's page stays 256-byte aligned
     char* base = nullptr;
     hipError_t e = hipMalloc((void**)&base, body + 2 * kGuard);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+      (void)hipGetLastError();  // reported by the caller; not a later launch's error
+      return e;
+    }
     if ((e = hipMemset(base, kGuardByte, body + 2 * kGuard)) != hipSuccess ||
         (e = hipMemset(base + kGuard, 0, bytes)) != hipSuccess) {
       (void)hipFree(base);
@@ -640,7 +646,11 @@ hipError_t dmalloc(void** p, size_t bytes) {
     return hipSuccess;
   }
   hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) { *p = nullptr; return e; }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // reported by the caller; not a later launch's error
+    *p = nullptr;
+    return e;
+  }
   return hipMemset(*p, 0, bytes);
 }
 
@@ -1933,6 +1943,7 @@ ns_status ns_create(const ns_params* params, int32_t n_instances, void* hip_stre
   s->timing = (params[0].flags & NS_TIMING) != 0;
   auto bail = [&](ns_status code, const std::string& m) {
     g_create_err = m;
+    (void)hipGetLastError();  // the failure is reported here, not by a later call
     ns_destroy(s);
     return code;
   };
