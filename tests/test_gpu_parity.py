@@ -325,6 +325,49 @@ def test_nonfinite_state_is_reported():
     assert "non-finite" in s.last_error()
 
 
+@pytest.mark.parametrize("variant", [dict(precision="mixed"), dict(integrator="rk2"),
+                                     dict(convection="advective"), dict(precision="mixed", integrator="rk2"),
+                                     dict(tile=(16, 0)), dict(tile=(-1, 0)), dict(dt=0.0, tau=0.5)])
+@pytest.mark.parametrize("field", ["u", "w", "p"])
+def test_nonfinite_state_is_reported_in_every_form(variant, field):
+    """A NaN in the velocity or the pressure is reported as NS_E_NONFINITE
+    by every form of the step (mixed precision, two-stage integrator,
+    advective form, every sweep family, adaptive dt), and the handle stays
+    usable: a finite state set afterwards steps normally."""
+    from paper_1201_2118_amd import abi
+    prm = dict(W.cavity(10, ny=9, nz=8), **variant)
+    init = U.random_state(prm, 4)
+    bad = {k: v.copy() for k, v in init.items()}
+    bad[field][4, 5, 5] = np.nan
+    s = U.gpu_run(prm, 0, bad)
+    assert s.step(2, check=False) == abi.NS_E_NONFINITE
+    assert "non-finite" in s.last_error()
+    for name, arr in init.items():
+        s.set(name, arr)
+    assert s.step(1, check=False) == abi.NS_OK, s.last_error()
+    for f in "uvwp":
+        assert np.isfinite(s.get_np(f)).all(), f
+    s.close()
+
+
+@pytest.mark.parametrize("launches", [0, 1])
+def test_nonfinite_state_is_reported_in_a_batch(launches):
+    """A NaN in one domain of a batched handle (persistent and multi-launch
+    form) is reported as NS_E_NONFINITE."""
+    from paper_1201_2118_amd import abi
+    from paper_1201_2118_amd.solver import Solver
+    prms = [dict(W.cavity(10 + i, ny=9, nz=8), precision="mixed") for i in range(3)]
+    s = Solver([dict(p, flags=abi.NS_BATCH_LAUNCHES if launches else 0) for p in prms])
+    for i, p in enumerate(prms):
+        init = U.random_state(p, 40 + i)
+        if i == 1:
+            init["v"][3, 4, 5] = np.nan
+        for name, arr in init.items():
+            s.set(name, arr, i)
+    assert s.step(2, check=False) == abi.NS_E_NONFINITE
+    s.close()
+
+
 # ---- mixed precision ---------------------------------------------------------------
 
 def test_mixed_matches_its_fp64_algorithm_and_fp64_oracle():
