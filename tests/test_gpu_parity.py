@@ -368,6 +368,28 @@ def test_nonfinite_state_is_reported_in_a_batch(launches):
     s.close()
 
 
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+@pytest.mark.parametrize("itermax", [1, 3])
+def test_unconverged_solves_are_counted(form, itermax):
+    """A sweep budget too small for the tolerance is not an error: every step
+    proceeds after itermax sweeps and counts as unconverged, as in the
+    oracle; a batched handle (persistent launch) counts per domain."""
+    from paper_1201_2118_amd.solver import Solver
+    prm = dict(W.cavity(14, ny=12, nz=10, tol=1e-12, itermax=itermax), precision=form)
+    s = U.gpu_run(prm, 4)
+    o, rc = U.oracle_run(dict(prm, precision="fp64"), 4, mode=1 if form == "mixed" else 0)
+    st = s.stats()
+    assert st["steps"] == 4 and st["steps_unconverged"] == o.stats.steps_unconverged == 4
+    assert st["sweeps_max"] == o.stats.sweeps_max == itermax
+    assert st["sweeps_total"] == o.stats.sweeps_total == 4 * itermax
+    b = Solver([prm, dict(prm, nx=12, tol=1e-3, itermax=200)])
+    b.step(4)
+    assert b.stats(0)["steps_unconverged"] == 4 and b.stats(0)["sweeps_total"] == 4 * itermax
+    assert b.stats(1)["steps_unconverged"] == 0
+    b.close()
+    s.close()
+
+
 # ---- mixed precision ---------------------------------------------------------------
 
 def test_mixed_matches_its_fp64_algorithm_and_fp64_oracle():
