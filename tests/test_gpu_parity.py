@@ -390,6 +390,23 @@ def test_unconverged_solves_are_counted(form, itermax):
     s.close()
 
 
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_unstable_dt_when_allowed_ends_nonfinite(form):
+    """A fixed dt 40 times the explicit diffusion bound, accepted with
+    NS_ALLOW_UNSTABLE: the state overflows within a few steps (the oracle's
+    run of the same case after 6), and ns_step reports NS_E_NONFINITE with
+    the completed steps counted -- an error code, not a crash."""
+    from paper_1201_2118_amd import abi
+    n, re = 12, 100.0
+    bound = 0.5 * re / (3 * n * n)  # diffusion number 1/2 on the unit cube
+    prm = dict(W.cavity(n, re=re, dt=40 * bound, itermax=50), precision=form, flags=abi.NS_ALLOW_UNSTABLE)
+    s = U.gpu_run(prm, 0, U.random_state(prm, 9, amp=0.1))
+    code = s.step(400, check=False)
+    assert code == abi.NS_E_NONFINITE, (code, s.last_error())
+    assert 0 < s.stats()["steps"] < 400
+    s.close()
+
+
 # ---- mixed precision ---------------------------------------------------------------
 
 def test_mixed_matches_its_fp64_algorithm_and_fp64_oracle():
