@@ -103,3 +103,39 @@ def test_host_pointer_backward_equals_device_backward():
     loss_o, grad_o, _ = oracle.gradient(prm, *u0, tgt, steps)
     for c in range(3):
         assert U.rel(gh[c], grad_o[c], mk[c]) < 1e-10, c
+
+
+def test_bad_arguments_on_a_live_handle():
+    """Argument errors on a live handle return NS_E_INVALID with a message and
+    leave the handle usable: an instance out of range, an unknown field id,
+    null data pointers, a negative step count, ns_backward without
+    recording."""
+    from paper_1201_2118_amd import abi
+    from paper_1201_2118_amd.solver import Solver
+    prm = W.cavity(10, ny=9, nz=8)
+    s = Solver([prm, prm])
+    h = s.handle
+    t = torch.zeros(s.shape(), dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    cases = [
+        (lambda: abi.ns_set_state(h, 2, abi.NS_U, t.data_ptr(), 1), "instance out of range"),
+        (lambda: abi.ns_get_state(h, -1, abi.NS_U, t.data_ptr(), 1), "instance out of range"),
+        (lambda: abi.ns_set_state(h, 0, 99, t.data_ptr(), 1), "unknown field id"),
+        (lambda: abi.ns_get_state(h, 1, -3, t.data_ptr(), 1), "unknown field id"),
+        (lambda: abi.ns_set_state(h, 0, abi.NS_P, None, 1), "src is NULL"),
+        (lambda: abi.ns_get_state(h, 0, abi.NS_P, None, 0), "dst is NULL"),
+        (lambda: abi.ns_step(h, -1, None), "nsteps must be >= 0"),
+    ]
+    for call, msg in cases:
+        assert call() == abi.NS_E_INVALID, msg
+        assert msg in abi.ns_last_error(h), (msg, abi.ns_last_error(h))
+    gi = [torch.zeros(s.shape(), dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    code = abi.ns_backward(h, 0, [g.data_ptr() for g in gi], [g.data_ptr() for g in gi], 1)
+    assert code == abi.NS_E_INVALID, code  # no recording (checkpoint_every = 0)
+    # still usable
+    s.step(2)
+    o, rc = U.oracle_run(prm, 2)
+    assert rc == 0
+    for i in range(2):
+        assert s.stats(i)["sweeps_total"] == o.stats.sweeps_total
+    s.close()
