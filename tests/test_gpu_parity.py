@@ -353,18 +353,27 @@ def test_nonfinite_state_is_reported_in_every_form(variant, field):
 @pytest.mark.parametrize("launches", [0, 1])
 def test_nonfinite_state_is_reported_in_a_batch(launches):
     """A NaN in one domain of a batched handle (persistent and multi-launch
-    form) is reported as NS_E_NONFINITE."""
+    form) is reported as NS_E_NONFINITE; with finite states set again the
+    handle steps normally."""
     from paper_1201_2118_amd import abi
     from paper_1201_2118_amd.solver import Solver
     prms = [dict(W.cavity(10 + i, ny=9, nz=8), precision="mixed") for i in range(3)]
     s = Solver([dict(p, flags=abi.NS_BATCH_LAUNCHES if launches else 0) for p in prms])
-    for i, p in enumerate(prms):
-        init = U.random_state(p, 40 + i)
-        if i == 1:
-            init["v"][3, 4, 5] = np.nan
+    inits = [U.random_state(p, 40 + i) for i, p in enumerate(prms)]
+    for i, init in enumerate(inits):
+        for name, arr in init.items():
+            a = arr.copy()
+            if i == 1 and name == "v":
+                a[3, 4, 5] = np.nan
+            s.set(name, a, i)
+    assert s.step(2, check=False) == abi.NS_E_NONFINITE
+    for i, init in enumerate(inits):
         for name, arr in init.items():
             s.set(name, arr, i)
-    assert s.step(2, check=False) == abi.NS_E_NONFINITE
+    assert s.step(1, check=False) == abi.NS_OK, s.last_error()
+    for i in range(3):
+        for f in "uvwp":
+            assert np.isfinite(s.get_np(f, i)).all(), (i, f)
     s.close()
 
 
