@@ -7,7 +7,6 @@ import os
 import re
 import subprocess
 
-import numpy as np
 import pytest
 
 import nsworkloads as W

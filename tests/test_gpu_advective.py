@@ -3,7 +3,6 @@ weighted by alpha = gamma) on the GPU against the oracle running the same
 form: the predictor alone (itermax 0) to 1e-13, whole steps to 1e-12 with
 equal sweep counts (FP64) and the mixed form to 1e-5, on wall, periodic
 and mixed-boundary grids with body-force fields and adaptive dt."""
-import numpy as np
 import pytest
 
 import nsworkloads as W

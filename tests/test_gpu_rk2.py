@@ -9,7 +9,6 @@ import numpy as np
 import pytest
 
 import nsworkloads as W
-import oracle
 from paper_1201_2118_amd import abi
 from tests import gpu_util as U
 
