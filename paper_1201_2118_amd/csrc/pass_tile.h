@@ -342,6 +342,10 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
     ebuf(0, SP)[e_top] = pm1[0];
     ebuf(0, SP)[e_bot] = pm1[R - 1];
     lds_barrier();
+    // FP32 tiles issue the plane's arithmetic at raised wave priority and drop
+    // it before the next plane's loads (measured 1 % faster single-domain and
+    // 2 % batched; FP64 tiles, two waves per SIMD, measured 1.5 % slower)
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(1);
     const T inA = ebuf(0, SP)[e_above], inB = ebuf(0, SP)[e_below];
     const T x1A = ebuf(1, SP ^ 1)[e_above], x1B = ebuf(1, SP ^ 1)[e_below];
 
@@ -467,6 +471,7 @@ __device__ __forceinline__ void pass_tile(const T* __restrict__ p_in, T* __restr
     const long pl = plane_of(L + kRing - 2);
     const Plane bp = plane_at(p_in, pl, g.sxy);
     const Plane br = plane_at(rhs, pl, g.sxy);
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int r = 0; r < R; r++) {
       pm2[r] = ZIN ? T(0) : ld_plane(bp, off[r], (T*)nullptr);
